@@ -1,0 +1,275 @@
+/*
+ * anon.h - C ABI of libanon.so, the MI355X (gfx950) NER + pseudonymize path.
+ *
+ * The library implements the data-parallel middle of the paper's pipeline
+ * (Sec. II): stage 2, token-classification NER with a transformer encoder,
+ * and stage 3, deterministic HMAC-SHA256 pseudonym substitution written as
+ * [TYPE_slug].  Everything between the packed token ids and the substituted
+ * bytes runs in HIP kernels on one GPU.
+ *
+ * Conventions
+ *   - Pointers named d_* are device memory owned by the caller.  Pointers
+ *     named h_* are host memory owned by the caller.  Opaque handles
+ *     (anon_model, anon_pcache, anon_server) are owned by the library.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream only enqueue work and return; results are
+ *     valid once the stream has been synchronised.
+ *   - Argument errors are reported synchronously with a negative status;
+ *     anon_last_error() then describes the problem (thread-local string).
+ *   - Problems found in device data (token id outside the vocabulary,
+ *     malformed cu_seqlens, labels outside [0, 2*n_types], malformed spans,
+ *     exceeded capacities) never cause an out-of-bounds access: the kernels
+ *     clamp or skip and raise a bit in the per-device error word read by
+ *     anon_device_errors().
+ *   - Packed varlen layout: B records, T tokens in total, record b owns
+ *     tokens [cu_seqlens[b], cu_seqlens[b+1]); cu_seqlens[0] = 0,
+ *     cu_seqlens[B] = T, no padding.
+ */
+#ifndef ANON_H
+#define ANON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ANON_OK = 0,
+  ANON_PENDING = 1,     /* anon_poll: request not finished yet            */
+  ANON_EINVAL = -1,     /* invalid argument                               */
+  ANON_ENOMEM = -2,     /* device or host allocation failed               */
+  ANON_EDEVICE = -3,    /* HIP runtime error                              */
+  ANON_ECAPACITY = -4,  /* a caller-provided buffer is too small          */
+  ANON_EBUSY = -5,      /* server queue full / budget exhausted           */
+  ANON_ENOTFOUND = -6,  /* unknown ticket                                 */
+  ANON_EDATA = -7       /* malformed device data (see anon_device_errors) */
+} anon_status;
+
+typedef enum { ANON_FP32 = 0, ANON_BF16 = 1, ANON_FP8_E4M3 = 2 } anon_precision;
+
+/* Bits of the per-device error word. */
+enum {
+  ANON_ERR_TOKEN_ID = 1,      /* token id >= vocab or < 0 (embedding row 0 used)   */
+  ANON_ERR_SEQLENS = 2,       /* cu_seqlens not monotone / record longer than max_pos */
+  ANON_ERR_LABEL = 4,         /* label > 2*n_types (token treated as O)             */
+  ANON_ERR_SPAN = 8,          /* span outside its record / overlapping (skipped)     */
+  ANON_ERR_SPAN_CAP = 16,     /* more spans than span_cap (extra spans dropped)      */
+  ANON_ERR_OUT_CAP = 32       /* output larger than out_cap (output truncated)       */
+};
+
+/* Encoder shape.  head_dim = hidden / n_heads must be 64; n_labels = 2*types+1. */
+typedef struct {
+  int32_t n_layers, hidden, n_heads, ffn, vocab, n_labels, max_pos;
+  float ln_eps;
+} anon_model_config;
+
+/* One entity span: bytes [begin, end) of record `record`, type in 1..n_types. */
+typedef struct {
+  int32_t record;
+  int32_t type;
+  int64_t begin;
+  int64_t end;
+} anon_span;
+
+typedef struct anon_model anon_model;
+typedef struct anon_pcache anon_pcache;
+typedef struct anon_server anon_server;
+
+/* Last error message of the calling thread ("" if none). */
+const char* anon_last_error(void);
+
+/* Library ABI version (increments on incompatible changes). */
+int32_t anon_version(void);
+
+/* Read (and if `clear`, reset) the error word of `device`.  Synchronises
+ * the device. */
+anon_status anon_device_errors(int32_t device, uint32_t* flags, int32_t clear);
+
+/* ------------------------------------------------------------------------
+ * Model (Sec. II stage 2: transformer token-classification NER)
+ * ------------------------------------------------------------------------
+ * anon_model_create uploads an encoder to `device`.
+ *   h_weights: n_floats FP32 values, the tensors back to back in this order
+ *     (matrices in "x @ W" orientation, i.e. [in, out], row-major):
+ *       tok_emb [vocab,h], pos_emb [max_pos,h], emb_ln_g [h], emb_ln_b [h],
+ *       per layer: wqkv [h,3h], bqkv [3h], wo [h,h], bo [h], ln1_g [h],
+ *                  ln1_b [h], w1 [h,ffn], b1 [ffn], w2 [ffn,h], b2 [h],
+ *                  ln2_g [h], ln2_b [h],
+ *       wc [h,n_labels], bc [n_labels].
+ *     Columns of wqkv are [Q | K | V]; head j owns columns j*64..j*64+63 of
+ *     each block.  The host array is only read during the call.
+ *   precision: FP32 (plain path), BF16, or FP8_E4M3 GEMMs.
+ *   h_act_scales: FP8 only: 4*n_layers static per-tensor scales of the GEMM
+ *     inputs (qkv, attention-out, ffn1, ffn2 per layer), each a power of two;
+ *     NULL otherwise.
+ * The returned model is used from one host thread at a time.
+ */
+anon_status anon_model_create(const anon_model_config* cfg, const float* h_weights, size_t n_floats,
+                              anon_precision precision, const float* h_act_scales, int32_t device,
+                              anon_model** out);
+void anon_model_free(anon_model* model);
+
+/* Device workspace bytes that ner_forward needs for a batch of T tokens in
+ * B records (an upper bound, valid for any batch with at most T tokens and B
+ * records). */
+anon_status anon_ner_workspace_size(const anon_model* model, int32_t T, int32_t B, size_t* bytes);
+
+/* NER forward pass over a packed batch (Sec. II stage 2).
+ *   d_ids        int32 [T]   token ids in [0, vocab)
+ *   d_cu_seqlens int32 [B+1] record boundaries; each record <= max_pos tokens
+ *   d_labels     uint8 [T]   out: argmax label per token (lowest index on ties)
+ *   d_logits     float [T, n_labels] out, or NULL
+ *   d_margin     float [T]   out: top-1 minus top-2 logit, or NULL
+ *   d_workspace  >= anon_ner_workspace_size(T, B) bytes, 256-byte aligned
+ * Positions restart at 0 for every record; attention never crosses records.
+ * Results do not depend on the other records of the batch. */
+anon_status ner_forward(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                        int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                        size_t ws_bytes, void* stream);
+
+/* Hidden state after the first n_layers layers (0 = after the embedding
+ * LayerNorm) as FP32 [T, hidden] in d_hidden: the activations ner_forward
+ * computes, exposed for layer-by-layer checking.  Same workspace rule. */
+anon_status anon_encoder_hidden(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                                int32_t T, int32_t n_layers, float* d_hidden, void* d_workspace, size_t ws_bytes,
+                                void* stream);
+
+/* Windowed NER for records longer than one window (the paper names
+ * truncation of long inputs as a limitation, Sec. VI).  A record of n tokens
+ * is covered by windows of `window` tokens starting every `stride` tokens
+ * (the last may be shorter); each token takes its logits from its owner
+ * window: in the overlap of windows k and k+1, the first (window-stride)/2
+ * tokens belong to k, the rest to k+1.  Positions restart in every window.
+ *   h_cu_seqlens: host copy of d_cu_seqlens (used to plan the windows).
+ * Outputs are per record token, as in ner_forward. */
+anon_status anon_ner_windowed_workspace_size(const anon_model* model, const int32_t* h_cu_seqlens, int32_t B,
+                                             int32_t window, int32_t stride, size_t* bytes);
+anon_status ner_forward_windowed(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens,
+                                 const int32_t* h_cu_seqlens, int32_t B, int32_t T, int32_t window, int32_t stride,
+                                 uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                                 size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * BIO span decoding (labels to entity byte ranges, input of Sec. II stage 3)
+ * ------------------------------------------------------------------------
+ * Label 0 = O; type t in 1..n_types has B-t = 2t-1, I-t = 2t.  O closes the
+ * open span; B-t opens a new one; I-t extends an open span of type t and
+ * otherwise opens a new one.  A span covers [begin of its first token, end of
+ * its last token).
+ *   d_tok_off    int32 [T, 2] byte range of each token inside its record
+ *   d_spans      out: up to span_cap spans, record-major, in token order
+ *   d_cu_spans   int32 [B+1] out: record b owns spans [cu_spans[b], cu_spans[b+1]);
+ *                cu_spans[B] is the total even when it exceeds span_cap.
+ *   d_workspace  >= anon_decode_workspace_size(T, B) bytes. */
+anon_status anon_decode_workspace_size(int32_t T, int32_t B, size_t* bytes);
+anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, const int32_t* d_cu_seqlens, int32_t B,
+                         int32_t T, int32_t n_types, anon_span* d_spans, int32_t span_cap, int32_t* d_cu_spans,
+                         void* d_workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Pseudonyms (Sec. II stage 3)
+ * ------------------------------------------------------------------------
+ * A pseudonym cache holds the HMAC key, the slug length (0..64 lowercase hex
+ * characters; 0 gives "[TYPE]"), the type names (type t is type_names[t-1],
+ * characters A-Z, 0-9 and '_', at most 32 bytes) and a device hash table
+ * mapping entity bytes to their HMAC-SHA256 digest (`capacity` slots, rounded
+ * up to a power of two; entities longer than 96 bytes bypass the table).  The
+ * table only changes how often HMAC is computed, never the output.  The
+ * pseudonym of an entity depends only on (key, entity bytes, type, slug
+ * length): the same entity gets the same pseudonym in every record and call. */
+anon_status anon_pcache_create(const uint8_t* h_key, size_t key_len, int32_t slug_hex,
+                               const char* const* type_names, int32_t n_types, int64_t capacity, int32_t device,
+                               anon_pcache** out);
+void anon_pcache_free(anon_pcache* cache);
+/* Empty the table and zero the counters (stream-ordered). */
+anon_status anon_pcache_clear(anon_pcache* cache, void* stream);
+/* Enable (1) or bypass (0) the table for later calls. */
+anon_status anon_pcache_set_enabled(anon_pcache* cache, int32_t enabled);
+/* Probes, probes that found a ready entry, and inserted entries since the
+ * last clear.  Synchronises the device. */
+anon_status anon_pcache_stats(anon_pcache* cache, int64_t* lookups, int64_t* hits, int64_t* entries);
+
+/* Substitute every span of every record.
+ *   d_text      uint8 record bytes back to back; record b is
+ *               d_text[cu_bytes[b] .. cu_bytes[b+1])
+ *   d_cu_bytes  int64 [B+1]
+ *   d_spans, d_cu_spans, span_cap: as written by decode_spans (spans of a
+ *               record must be sorted, disjoint and inside the record;
+ *               others are skipped and flagged)
+ *   d_out       uint8 [out_cap] out: record b is d_out[cu_out[b] .. cu_out[b+1])
+ *   d_cu_out    int64 [B+1] out; cu_out[B] is the total length even when it
+ *               exceeds out_cap (then the output is truncated and flagged)
+ *   d_workspace >= anon_pseudonymize_workspace_size(B, span_cap) bytes. */
+anon_status anon_pseudonymize_workspace_size(int32_t B, int32_t span_cap, size_t* bytes);
+anon_status pseudonymize(anon_pcache* cache, const uint8_t* d_text, const int64_t* d_cu_bytes, int32_t B,
+                         const anon_span* d_spans, const int32_t* d_cu_spans, int32_t span_cap, uint8_t* d_out,
+                         int64_t out_cap, int64_t* d_cu_out, void* d_workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of record batches (submit / poll)
+ * ------------------------------------------------------------------------
+ * A server thread admits queued requests while their activation footprint
+ * fits `hbm_budget_bytes` and a stream slot is free, packs them into
+ * micro-batches of at most `max_batch_tokens` tokens, runs NER, span
+ * decoding and substitution on one of `n_streams` streams, and copies the
+ * results back.  Requests that arrive while others run are admitted as soon
+ * as budget and a slot free up.  A request's result does not depend on the
+ * requests it was batched with. */
+typedef struct {
+  int64_t hbm_budget_bytes;   /* activation budget (e.g. 64 GiB)          */
+  int32_t max_batch_tokens;   /* tokens per micro-batch                    */
+  int32_t n_streams;          /* micro-batches in flight (1..8)            */
+  int32_t max_queue;          /* queued requests before anon_submit EBUSY  */
+  int32_t max_request_tokens; /* larger requests are rejected (EINVAL)     */
+} anon_server_config;
+
+/* One request: n_records records with host arrays (copied before return). */
+typedef struct {
+  int32_t n_records;
+  const int32_t* ids;         /* [T]          */
+  const int32_t* cu_seqlens;  /* [n_records+1] */
+  const int32_t* tok_off;     /* [T, 2]       */
+  const uint8_t* text;        /* [cu_bytes[n_records]] */
+  const int64_t* cu_bytes;    /* [n_records+1] */
+} anon_request;
+
+/* Result of a finished request; buffers stay valid until anon_release. */
+typedef struct {
+  int32_t status;             /* ANON_OK or a negative anon_status        */
+  int32_t n_records;
+  int32_t n_tokens;
+  int32_t n_spans;
+  const uint8_t* out;         /* substituted bytes                         */
+  const int64_t* cu_out;      /* [n_records+1]                             */
+  const uint8_t* labels;      /* [n_tokens]                                */
+  const anon_span* spans;     /* [n_spans], record index local to request  */
+  double t_submit, t_start, t_done;  /* seconds, steady clock             */
+} anon_result;
+
+anon_status anon_server_start(anon_model* model, anon_pcache* cache, const anon_server_config* cfg,
+                              anon_server** out);
+anon_status anon_submit(anon_server* server, const anon_request* req, uint64_t* ticket);
+/* ANON_PENDING while running; ANON_OK once `out` is filled. */
+anon_status anon_poll(anon_server* server, uint64_t ticket, anon_result* out);
+anon_status anon_release(anon_server* server, uint64_t ticket);
+/* Finishes in-flight work, fails queued requests, joins the thread. */
+anon_status anon_server_stop(anon_server* server);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support)
+ * ------------------------------------------------------------------------
+ * While enabled, the library brackets every launch of the kernel class
+ * `kclass` with HIP events on the launch stream and accumulates the elapsed
+ * time; anon_prof_read synchronises and returns launches, total milliseconds
+ * and the algorithmic FLOPs of those launches.  Classes: 0 QKV GEMM,
+ * 1 attention, 2 output-projection GEMM, 3 FFN1 GEMM, 4 FFN2 GEMM,
+ * 5 LayerNorm, 6 embedding, 7 classifier. */
+anon_status anon_prof_enable(int32_t kclass, int32_t enabled);
+anon_status anon_prof_read(int32_t kclass, int64_t* launches, double* total_ms, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ANON_H */

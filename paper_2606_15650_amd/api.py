@@ -1,0 +1,345 @@
+"""ctypes binding of libanon.so (include/anon.h).
+
+Argument marshalling only: every step of the NER + pseudonymize path runs in
+the library's HIP kernels.  Device buffers are torch tensors on a ROCm device
+(or raw integer device addresses); streams are torch streams (or raw
+hipStream_t handles).  If libanon.so is missing the import of the library
+fails loudly - there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libanon.so")
+
+ANON_OK, ANON_PENDING = 0, 1
+STATUS = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY",
+          -5: "EBUSY", -6: "ENOTFOUND", -7: "EDATA"}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
+ERR_TOKEN_ID, ERR_SEQLENS, ERR_LABEL, ERR_SPAN, ERR_SPAN_CAP, ERR_OUT_CAP = 1, 2, 4, 8, 16, 32
+KCLASS = {"qkv": 0, "attn": 1, "oproj": 2, "ffn1": 3, "ffn2": 4, "ln": 5, "embed": 6, "cls": 7}
+
+
+class AnonError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ModelConfigC(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("hidden", C.c_int32), ("n_heads", C.c_int32), ("ffn", C.c_int32),
+                ("vocab", C.c_int32), ("n_labels", C.c_int32), ("max_pos", C.c_int32), ("ln_eps", C.c_float)]
+
+
+class SpanC(C.Structure):
+    _fields_ = [("record", C.c_int32), ("type", C.c_int32), ("begin", C.c_int64), ("end", C.c_int64)]
+
+
+SPAN_BYTES = C.sizeof(SpanC)  # 24
+
+
+class ServerConfigC(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch_tokens", C.c_int32), ("n_streams", C.c_int32),
+                ("max_queue", C.c_int32), ("max_request_tokens", C.c_int32)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("n_records", C.c_int32), ("ids", C.POINTER(C.c_int32)), ("cu_seqlens", C.POINTER(C.c_int32)),
+                ("tok_off", C.POINTER(C.c_int32)), ("text", C.POINTER(C.c_uint8)),
+                ("cu_bytes", C.POINTER(C.c_int64))]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_records", C.c_int32), ("n_tokens", C.c_int32), ("n_spans", C.c_int32),
+                ("out", C.POINTER(C.c_uint8)), ("cu_out", C.POINTER(C.c_int64)), ("labels", C.POINTER(C.c_uint8)),
+                ("spans", C.POINTER(SpanC)), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+
+_lib = None
+vp, sz, i32, i64, u64 = C.c_void_p, C.c_size_t, C.c_int32, C.c_int64, C.c_uint64
+_SIGS = {
+    "anon_last_error": ([], C.c_char_p),
+    "anon_version": ([], i32),
+    "anon_device_errors": ([i32, C.POINTER(C.c_uint32), i32], i32),
+    "anon_model_create": ([C.POINTER(ModelConfigC), vp, sz, i32, vp, i32, C.POINTER(vp)], i32),
+    "anon_model_free": ([vp], None),
+    "anon_ner_workspace_size": ([vp, i32, i32, C.POINTER(sz)], i32),
+    "ner_forward": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], i32),
+    "anon_encoder_hidden": ([vp, vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
+    "anon_ner_windowed_workspace_size": ([vp, vp, i32, i32, i32, C.POINTER(sz)], i32),
+    "ner_forward_windowed": ([vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
+    "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
+    "decode_spans": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+    "anon_pcache_create": ([vp, sz, i32, C.POINTER(C.c_char_p), i32, i64, i32, C.POINTER(vp)], i32),
+    "anon_pcache_free": ([vp], None),
+    "anon_pcache_clear": ([vp, vp], i32),
+    "anon_pcache_set_enabled": ([vp, i32], i32),
+    "anon_pcache_stats": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], i32),
+    "anon_pseudonymize_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
+    "pseudonymize": ([vp, vp, vp, i32, vp, vp, i32, vp, i64, vp, vp, sz, vp], i32),
+    "anon_server_start": ([vp, vp, C.POINTER(ServerConfigC), C.POINTER(vp)], i32),
+    "anon_submit": ([vp, C.POINTER(RequestC), C.POINTER(u64)], i32),
+    "anon_poll": ([vp, u64, C.POINTER(ResultC)], i32),
+    "anon_release": ([vp, u64], i32),
+    "anon_server_stop": ([vp], i32),
+    "anon_prof_enable": ([i32, i32], i32),
+    "anon_prof_read": ([i32, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
+}
+EXPORTED = sorted(_SIGS)
+
+
+def lib() -> C.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2606_15650_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, st: int) -> int:
+    if st < 0:
+        raise AnonError(fn, st, lib().anon_last_error().decode(errors="replace"))
+    return st
+
+
+def ptr(x) -> int | None:
+    """Device address of a torch tensor / integer / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def stream_handle(stream=None) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ model --
+class Model:
+    """An encoder uploaded to one device (``anon_model_create``)."""
+
+    def __init__(self, cfg, weights_blob: np.ndarray, precision: str = "bf16", act_scales=None, device: int = 0):
+        blob = np.ascontiguousarray(weights_blob, dtype=np.float32)
+        self.cfg = cfg
+        self.precision = precision
+        c = ModelConfigC(cfg.n_layers, cfg.hidden, cfg.n_heads, cfg.ffn, cfg.vocab, cfg.n_labels, cfg.max_pos,
+                         cfg.ln_eps)
+        sc = None
+        if act_scales is not None:
+            self._scales = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32).reshape(-1))
+            sc = self._scales.ctypes.data
+        h = vp()
+        _check("anon_model_create", lib().anon_model_create(C.byref(c), blob.ctypes.data, blob.size,
+                                                            PRECISION[precision], sc, device, C.byref(h)))
+        self.handle = h.value
+        self.device = device
+
+    def workspace_size(self, T: int, B: int) -> int:
+        n = sz()
+        _check("anon_ner_workspace_size", lib().anon_ner_workspace_size(self.handle, T, B, C.byref(n)))
+        return n.value
+
+    def windowed_workspace_size(self, cu_seqlens: np.ndarray, window: int, stride: int) -> int:
+        cu = np.ascontiguousarray(cu_seqlens, dtype=np.int32)
+        n = sz()
+        _check("anon_ner_windowed_workspace_size",
+               lib().anon_ner_windowed_workspace_size(self.handle, cu.ctypes.data, cu.size - 1, window, stride,
+                                                      C.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().anon_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ner_forward(model: Model, d_ids, d_cu_seqlens, B: int, T: int, d_labels, d_logits=None, d_margin=None,
+                d_workspace=None, ws_bytes: int = 0, stream=None):
+    _check("ner_forward", lib().ner_forward(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T, ptr(d_labels),
+                                            ptr(d_logits), ptr(d_margin), ptr(d_workspace), ws_bytes,
+                                            stream_handle(stream)))
+
+
+def encoder_hidden(model: Model, d_ids, d_cu_seqlens, B: int, T: int, n_layers: int, d_hidden, d_workspace,
+                   ws_bytes: int, stream=None):
+    _check("anon_encoder_hidden", lib().anon_encoder_hidden(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T,
+                                                            n_layers, ptr(d_hidden), ptr(d_workspace), ws_bytes,
+                                                            stream_handle(stream)))
+
+
+def ner_forward_windowed(model: Model, d_ids, d_cu_seqlens, h_cu_seqlens: np.ndarray, B: int, T: int, window: int,
+                         stride: int, d_labels, d_logits=None, d_margin=None, d_workspace=None, ws_bytes: int = 0,
+                         stream=None):
+    cu = np.ascontiguousarray(h_cu_seqlens, dtype=np.int32)
+    _check("ner_forward_windowed",
+           lib().ner_forward_windowed(model.handle, ptr(d_ids), ptr(d_cu_seqlens), cu.ctypes.data, B, T, window,
+                                      stride, ptr(d_labels), ptr(d_logits), ptr(d_margin), ptr(d_workspace),
+                                      ws_bytes, stream_handle(stream)))
+
+
+def decode_workspace_size(T: int, B: int) -> int:
+    n = sz()
+    _check("anon_decode_workspace_size", lib().anon_decode_workspace_size(T, B, C.byref(n)))
+    return n.value
+
+
+def decode_spans(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int, d_spans, span_cap: int,
+                 d_cu_spans, d_workspace, ws_bytes: int, stream=None):
+    _check("decode_spans", lib().decode_spans(ptr(d_labels), ptr(d_tok_off), ptr(d_cu_seqlens), B, T, n_types,
+                                              ptr(d_spans), span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,
+                                              stream_handle(stream)))
+
+
+# ------------------------------------------------------------- pseudonyms --
+class PseudonymCache:
+    """HMAC key, slug length, type names and the device entity->digest table."""
+
+    def __init__(self, key: bytes, slug_hex: int, type_names, capacity: int = 1 << 20, device: int = 0):
+        names = (C.c_char_p * len(type_names))(*[n.encode() for n in type_names])
+        kb = (C.c_uint8 * max(1, len(key))).from_buffer_copy(key or b"\0")
+        h = vp()
+        _check("anon_pcache_create", lib().anon_pcache_create(C.addressof(kb), len(key), slug_hex, names,
+                                                              len(type_names), capacity, device, C.byref(h)))
+        self.handle = h.value
+        self.type_names = list(type_names)
+        self.slug = slug_hex
+
+    def clear(self, stream=None):
+        _check("anon_pcache_clear", lib().anon_pcache_clear(self.handle, stream_handle(stream)))
+
+    def set_enabled(self, on: bool):
+        _check("anon_pcache_set_enabled", lib().anon_pcache_set_enabled(self.handle, 1 if on else 0))
+
+    def stats(self) -> dict:
+        a, b, c = i64(), i64(), i64()
+        _check("anon_pcache_stats", lib().anon_pcache_stats(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return {"lookups": a.value, "hits": b.value, "entries": c.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().anon_pcache_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pseudonymize_workspace_size(B: int, span_cap: int) -> int:
+    n = sz()
+    _check("anon_pseudonymize_workspace_size", lib().anon_pseudonymize_workspace_size(B, span_cap, C.byref(n)))
+    return n.value
+
+
+def pseudonymize(cache: PseudonymCache, d_text, d_cu_bytes, B: int, d_spans, d_cu_spans, span_cap: int, d_out,
+                 out_cap: int, d_cu_out, d_workspace, ws_bytes: int, stream=None):
+    _check("pseudonymize", lib().pseudonymize(cache.handle, ptr(d_text), ptr(d_cu_bytes), B, ptr(d_spans),
+                                              ptr(d_cu_spans), span_cap, ptr(d_out), out_cap, ptr(d_cu_out),
+                                              ptr(d_workspace), ws_bytes, stream_handle(stream)))
+
+
+def device_errors(device: int = 0, clear: bool = True) -> int:
+    f = C.c_uint32()
+    _check("anon_device_errors", lib().anon_device_errors(device, C.byref(f), 1 if clear else 0))
+    return f.value
+
+
+# ------------------------------------------------------------------ timing --
+def prof_enable(kclass: str, on: bool = True):
+    _check("anon_prof_enable", lib().anon_prof_enable(KCLASS[kclass], 1 if on else 0))
+
+
+def prof_read(kclass: str) -> dict:
+    n, ms, fl = i64(), C.c_double(), C.c_double()
+    _check("anon_prof_read", lib().anon_prof_read(KCLASS[kclass], C.byref(n), C.byref(ms), C.byref(fl)))
+    return {"launches": n.value, "ms": ms.value, "flops": fl.value}
+
+
+# ------------------------------------------------------------------ server --
+class Server:
+    """Continuous-batching server (anon_server_start / submit / poll)."""
+
+    def __init__(self, model: Model, cache: PseudonymCache, hbm_budget_bytes: int = 64 << 30,
+                 max_batch_tokens: int = 131072, n_streams: int = 2, max_queue: int = 4096,
+                 max_request_tokens: int = 0):
+        cfg = ServerConfigC(hbm_budget_bytes, max_batch_tokens, n_streams, max_queue, max_request_tokens)
+        h = vp()
+        _check("anon_server_start", lib().anon_server_start(model.handle, cache.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h.value
+        self._keep = (model, cache)
+
+    def submit(self, ids: np.ndarray, cu_seqlens: np.ndarray, tok_off: np.ndarray, text: bytes,
+               cu_bytes: np.ndarray) -> int:
+        ids = np.ascontiguousarray(ids, np.int32)
+        cu = np.ascontiguousarray(cu_seqlens, np.int32)
+        off = np.ascontiguousarray(tok_off, np.int32)
+        cb = np.ascontiguousarray(cu_bytes, np.int64)
+        tb = np.frombuffer(text, dtype=np.uint8) if len(text) else np.zeros(1, np.uint8)
+        req = RequestC(cu.size - 1, ids.ctypes.data_as(C.POINTER(C.c_int32)),
+                       cu.ctypes.data_as(C.POINTER(C.c_int32)), off.ctypes.data_as(C.POINTER(C.c_int32)),
+                       tb.ctypes.data_as(C.POINTER(C.c_uint8)), cb.ctypes.data_as(C.POINTER(C.c_int64)))
+        t = u64()
+        _check("anon_submit", lib().anon_submit(self.handle, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else a dict with the request's outputs (copied)."""
+        r = ResultC()
+        st = _check("anon_poll", lib().anon_poll(self.handle, ticket, C.byref(r)))
+        if st == ANON_PENDING:
+            return None
+        out = {"status": r.status, "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done,
+               "n_records": r.n_records}
+        if r.status == ANON_OK:
+            cu = np.ctypeslib.as_array(r.cu_out, shape=(r.n_records + 1,)).copy()
+            n = int(cu[-1])
+            out["cu_out"] = cu
+            out["out"] = C.string_at(r.out, n) if n else b""
+            out["labels"] = (np.ctypeslib.as_array(r.labels, shape=(r.n_tokens,)).copy()
+                             if r.n_tokens else np.zeros(0, np.uint8))
+            sp = np.zeros((r.n_spans, 4), np.int64)
+            for i in range(r.n_spans):
+                s = r.spans[i]
+                sp[i] = (s.record, s.type, s.begin, s.end)
+            out["spans"] = sp
+        return out
+
+    def release(self, ticket: int):
+        _check("anon_release", lib().anon_release(self.handle, ticket))
+
+    def stop(self):
+        if getattr(self, "handle", None):
+            _check("anon_server_stop", lib().anon_server_stop(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

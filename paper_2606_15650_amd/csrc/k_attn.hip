@@ -1,0 +1,276 @@
+// Varlen self-attention over packed records (no padding), head dim 64.
+//
+// For each record and head: A = softmax(Q K^T / sqrt(d)) V over the keys of
+// the same record only (bidirectional encoder attention).  Q already carries
+// the 1/sqrt(d) = 1/8 factor (applied exactly in the QKV GEMM epilogue).
+//
+// Work item = (q-block of 32*WAVES rows of one record, head).  The block
+// streams the record's keys in tiles of 64: K rows and V^T are staged in LDS
+// and shared by all waves; each wave owns 32 query rows and computes
+// S^T = K Q^T with 32x32 MFMAs, so that every lane holds the scores of one
+// query row.  Softmax is online in FP32 (running max and sum per row, base-2
+// exponentials); the probabilities are rounded to the operand type and
+// O^T += V^T P^T accumulates in FP32.  The MFMA k-index of P^T is a
+// permutation of the 32 keys of a block; V^T is read from LDS with the same
+// permutation, so the contraction is exact.
+#include "kernels.hpp"
+
+namespace anon {
+namespace {
+
+template <typename T>
+struct AMfma;
+template <>
+struct AMfma<float> {
+  typedef float frag;
+  static constexpr int KI = 2, KPL = 1;
+  __device__ static floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct AMfma<bf16_t> {
+  typedef bf16x8 frag;
+  static constexpr int KI = 16, KPL = 8;
+  __device__ static floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ void st(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st(bf16_t* p, float v) { *p = static_cast<bf16_t>(v); }
+__device__ __forceinline__ void st(fp8_t* p, float v) { p->v = f32_to_e4m3(v); }
+
+constexpr int D = 64;    // head dim
+constexpr int KT = 64;   // keys per LDS tile
+
+// V^T fragment of PV step `st` in key block `kb` for lane half hh.
+__device__ __forceinline__ float vfrag(const float* vrow, int kb, int st, int hh) {
+  const int r = st;  // KPL = 1
+  return vrow[kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3)];
+}
+__device__ __forceinline__ bf16x8 vfrag(const bf16_t* vrow, int kb, int st, int hh) {
+  // registers 8*st .. 8*st+7 hold keys kb*32 + 16*st + hh*4 + {0..3} and
+  // kb*32 + 16*st + 8 + hh*4 + {0..3}
+  const bf16x4 lo = *(const bf16x4*)(vrow + kb * 32 + 16 * st + hh * 4);
+  const bf16x4 hi = *(const bf16x4*)(vrow + kb * 32 + 16 * st + 8 + hh * 4);
+  return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+template <typename T>
+__device__ __forceinline__ typename AMfma<T>::frag pfrag(const floatx16& s, int st);
+template <>
+__device__ __forceinline__ float pfrag<float>(const floatx16& s, int st) {
+  return s[st];
+}
+template <>
+__device__ __forceinline__ bf16x8 pfrag<bf16_t>(const floatx16& s, int st) {
+  bf16x8 f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) f[j] = static_cast<bf16_t>(s[st * 8 + j]);
+  return f;
+}
+
+template <typename T, typename TO, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ qkv, TO* __restrict__ out,
+                                                          const int4* __restrict__ qblocks,
+                                                          const int* __restrict__ n_qblocks, int hidden,
+                                                          float out_inv_scale) {
+  typedef AMfma<T> MF;
+  typedef typename MF::frag frag;
+  constexpr int NT = WAVES * 64;
+  constexpr int EPC = 16 / (int)sizeof(T);
+  constexpr int PAD = EPC;
+  constexpr float LOG2E = 1.4426950408889634f;
+
+  const int qb = blockIdx.x;
+  if (qb >= *n_qblocks) return;
+  const int head = blockIdx.y;
+  const int4 desc = qblocks[qb];  // (first token, length, first query row, -)
+  const int base = desc.x, L = desc.y, q0 = desc.z;
+  const int ld = 3 * hidden;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5;
+  const int qw = q0 + wave * 32;
+  const bool active = qw < L;
+
+  __shared__ T Ks[KT * (D + PAD)];
+  __shared__ T Vt[D * (KT + PAD)];
+
+  frag qf[D / MF::KI];
+  const int qrow = qw + (lane & 31);
+#pragma unroll
+  for (int kk = 0; kk < D / MF::KI; ++kk) {
+    if (qrow < L) {
+      qf[kk] = *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * MF::KI + hh * MF::KPL);
+    } else {
+      qf[kk] = frag{};
+    }
+  }
+
+  floatx16 o[2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
+  float m = -INFINITY, lsum = 0.f;
+
+  constexpr int CPR = D / EPC;  // 16-byte chunks per K/V row
+  for (int t0 = 0; t0 < L; t0 += KT) {
+    const int nk = min(KT, L - t0);
+    __syncthreads();
+    for (int c = tid; c < KT * CPR; c += NT) {
+      const int r = c / CPR, cc = c % CPR;
+      intx4 kv = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
+      if (r < nk) {
+        const T* src = qkv + (size_t)(base + t0 + r) * ld + head * D + cc * EPC;
+        kv = *(const intx4*)(src + hidden);
+        vv = *(const intx4*)(src + 2 * hidden);
+      }
+      *(intx4*)&Ks[r * (D + PAD) + cc * EPC] = kv;
+      const T* ve = (const T*)&vv;
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) Vt[(cc * EPC + e) * (KT + PAD) + r] = ve[e];
+    }
+    __syncthreads();
+    if (active) {
+      floatx16 s[2];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < D / MF::KI; ++kk) {
+          const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * (D + PAD) + kk * MF::KI + hh * MF::KPL];
+          s[kb] = MF::mma(a, qf[kk], s[kb]);
+        }
+      }
+      float mloc = -INFINITY;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
+          const float v = key < nk ? s[kb][r] * LOG2E : -INFINITY;
+          s[kb][r] = v;
+          mloc = fmaxf(mloc, v);
+        }
+      mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
+      const float mnew = fmaxf(m, mloc);
+      const float alpha = exp2f(m - mnew);
+      m = mnew;
+      float ps = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float pv = exp2f(s[kb][r] - mnew);
+          s[kb][r] = pv;
+          ps += pv;
+        }
+      lsum = lsum * alpha + ps;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        o[0][r] *= alpha;
+        o[1][r] *= alpha;
+      }
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int stp = 0; stp < 32 / MF::KI; ++stp) {
+          const frag pb = pfrag<T>(s[kb], stp);
+#pragma unroll
+          for (int db = 0; db < 2; ++db) {
+            const frag va = vfrag(&Vt[(db * 32 + (lane & 31)) * (KT + PAD)], kb, stp, hh);
+            o[db] = MF::mma(va, pb, o[db]);
+          }
+        }
+    }
+  }
+  if (active) {
+    const float ltot = lsum + __shfl_xor(lsum, 32, 64);
+    const float inv = out_inv_scale / ltot;
+    if (qrow < L) {
+      TO* dst = out + (size_t)(base + qrow) * hidden + head * D;
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), o[db][r] * inv);
+    }
+  }
+}
+
+constexpr int kWaves = 4;
+constexpr int kBQ = 32 * kWaves;
+
+// One workgroup: validates cu_seqlens and lists (record, q-block) items.
+__global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
+                                                        int bq, int4* __restrict__ qblocks, int max_q,
+                                                        int* __restrict__ n_qblocks, uint32_t* err) {
+  // Malformed (overlapping) cu_seqlens could ask for more items than the
+  // buffer holds; writes stop at max_q and the error bit is raised.
+  __shared__ int sums[1024];
+  const int tid = threadIdx.x;
+  const int per = (B + 1023) / 1024;
+  const int s0 = min(B, tid * per), s1 = min(B, s0 + per);
+  int cnt = 0;
+  bool bad = false;
+  for (int s = s0; s < s1; ++s) {
+    const int a = cu[s], b = cu[s + 1];
+    const int L = b - a;
+    if (a < 0 || b > T || L < 0 || L > max_len) {
+      bad = true;
+      continue;
+    }
+    cnt += (L + bq - 1) / bq;
+  }
+  if (tid == 0 && (cu[0] != 0 || cu[B] != T)) bad = true;
+  if (bad) raise_error(err, ANON_ERR_SEQLENS);
+  sums[tid] = cnt;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = tid >= o ? sums[tid - o] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  int pos = sums[tid] - cnt;
+  for (int s = s0; s < s1; ++s) {
+    const int a = cu[s], b = cu[s + 1];
+    const int L = b - a;
+    if (a < 0 || b > T || L < 0 || L > max_len) continue;
+    for (int q = 0; q < L && pos < max_q; q += bq) qblocks[pos++] = int4{a, L, q, s};
+  }
+  if (tid == 1023) {
+    const int total = sums[1023];
+    if (total > max_q) raise_error(err, ANON_ERR_SEQLENS);
+    *n_qblocks = min(total, max_q);
+  }
+}
+
+}  // namespace
+
+int attn_block_q(ElemType) { return kBQ; }
+
+void launch_seq_plan(const int* cu_seqlens, int B, int T, int max_len, int bq, int4* qblocks, int max_q,
+                     int* n_qblocks, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, bq, qblocks, max_q,
+                     n_qblocks, err);
+}
+
+void launch_attention(const void* qkv, void* out, const int4* qblocks,
+                      const int* n_qblocks, int max_qblocks, int n_heads, int hidden, ElemType t, ElemType out_t,
+                      float out_inv_scale, hipStream_t s) {
+  if (max_qblocks <= 0) return;
+  dim3 grid(max_qblocks, n_heads);
+  const int4* qb = qblocks;
+  if (t == ET_F32) {
+    hipLaunchKernelGGL((attn_kernel<float, float, kWaves>), grid, dim3(kWaves * 64), 0, s, (const float*)qkv,
+                       (float*)out, qb, n_qblocks, hidden, out_inv_scale);
+  } else if (out_t == ET_FP8) {
+    hipLaunchKernelGGL((attn_kernel<bf16_t, fp8_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
+                       (fp8_t*)out, qb, n_qblocks, hidden, out_inv_scale);
+  } else {
+    hipLaunchKernelGGL((attn_kernel<bf16_t, bf16_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
+                       (bf16_t*)out, qb, n_qblocks, hidden, out_inv_scale);
+  }
+}
+
+}  // namespace anon

@@ -1,0 +1,324 @@
+// Dense GEMMs of the encoder on CDNA4 matrix cores, with fused epilogues.
+//
+// C[M,N] = A[M,K] * W[N,K]^T, A = packed token activations (no padding), W =
+// a weight matrix stored transposed so that both operands are K-contiguous.
+// One workgroup owns a BM x BN output tile; its waves form a WGM x WGN grid
+// and each wave accumulates (BM/WGM) x (BN/WGN) with 32x32 MFMA tiles:
+//   fp32: v_mfma_f32_32x32x2_f32      (K step 2)
+//   bf16: v_mfma_f32_32x32x16_bf16    (K step 16)
+//   fp8 : v_mfma_scale_f32_32x32x64_f8f6f4 with E4M3 operands (K step 64)
+// A and W tiles are staged through double-buffered, row-padded LDS; the next
+// K tile is fetched into registers while the current one is multiplied.
+// The K loop always runs in increasing k with one MFMA shape per precision,
+// so each output element's sum is formed in the same order whatever the tile
+// shape or the row's position in the batch (batch invariance).
+//
+// Epilogues: bias (+ exact scaling of the Q columns by 1/sqrt(d)); bias + GELU;
+// bias + residual into an FP32 pre-LayerNorm buffer.
+#include "kernels.hpp"
+
+namespace anon {
+namespace {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  typedef float frag;
+  static constexpr int KI = 2, KPL = 1;
+  __device__ static floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<bf16_t> {
+  typedef bf16x8 frag;
+  static constexpr int KI = 16, KPL = 8;
+  __device__ static floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<fp8_t> {
+  typedef intx8 frag;
+  static constexpr int KI = 64, KPL = 32;
+  // operand formats 0/0 = E4M3 x E4M3; block scales 127 = 2^0 (unscaled)
+  __device__ static floatx16 mma(frag a, frag b, floatx16 c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+
+__device__ __forceinline__ float ld(const float* p) { return *p; }
+__device__ __forceinline__ float ld(const bf16_t* p) { return static_cast<float>(*p); }
+__device__ __forceinline__ void st(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st(bf16_t* p, float v) { *p = static_cast<bf16_t>(v); }
+__device__ __forceinline__ void st(fp8_t* p, float v) { p->v = f32_to_e4m3(v); }
+
+__device__ __forceinline__ float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so that the tiles sharing an A row-block (and the
+// weight panel) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int X = 8;
+  const int per = nb / X, rem = nb % X;
+  const int x = bid % X, loc = bid / X;
+  return x * per + min(x, rem) + loc;
+}
+
+struct DevParams {
+  const void* A;
+  const void* W;
+  const float* bias;
+  const void* resid;
+  void* C;
+  int M, N, K;
+  float qscale;
+  int qcols;
+  float acc_scale;
+  float out_inv_scale;
+};
+
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN>
+__global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
+  typedef Mfma<TI> MF;
+  typedef typename MF::frag frag;
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TM = WTM / 32, TN = WTN / 32;
+  constexpr int EPC = 16 / (int)sizeof(TI);  // elements per 16-byte chunk
+  constexpr int CPR = BK / EPC;              // chunks per tile row
+  constexpr int LDK = BK + EPC;              // padded LDS row (16 bytes)
+  constexpr int A_CH = BM * CPR / NT, B_CH = BN * CPR / NT;
+  static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "tile/threads mismatch");
+  static_assert(TM >= 1 && TN >= 1 && BK % MF::KI == 0, "bad tile");
+
+  __shared__ TI As[2][BM * LDK];
+  __shared__ TI Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int M = p.M, N = p.N, K = p.K;
+  const int ntn = N / BN;
+  const int ntm = (M + BM - 1) / BM;
+  const int tile = xcd_remap(blockIdx.x, ntm * ntn);
+  const int m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+
+  const TI* __restrict__ A = (const TI*)p.A;
+  const TI* __restrict__ W = (const TI*)p.W;
+
+  intx4 ra[A_CH], rb[B_CH];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+      const int c = tid + i * NT, r = c / CPR, cc = c % CPR;
+      const int gm = m0 + r;
+      if (gm < M)
+        ra[i] = *(const intx4*)(A + (size_t)gm * K + k0 + cc * EPC);
+      else
+        ra[i] = intx4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+      const int c = tid + i * NT, r = c / CPR, cc = c % CPR;
+      rb[i] = *(const intx4*)(W + (size_t)(n0 + r) * K + k0 + cc * EPC);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+      const int c = tid + i * NT, r = c / CPR, cc = c % CPR;
+      *(intx4*)&As[buf][r * LDK + cc * EPC] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+      const int c = tid + i * NT, r = c / CPR, cc = c % CPR;
+      *(intx4*)&Bs[buf][r * LDK + cc * EPC] = rb[i];
+    }
+  };
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = K / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int arow = wm * WTM + (lane & 31), brow = wn * WTN + (lane & 31);
+  const int kofs = (lane >> 5) * MF::KPL;
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / MF::KI; ++ks) {
+      frag a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = *(const frag*)&As[buf][(arow + i * 32) * LDK + ks * MF::KI + kofs];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = *(const frag*)&Bs[buf][(brow + j * 32) * LDK + ks * MF::KI + kofs];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < KT) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: lane owns column (lane & 31) of each 32x32 tile and rows
+  // (r/4)*8 + (lane/32)*4 + r%4 of accumulator register r.
+  TO* __restrict__ C = (TO*)p.C;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = n0 + wn * WTN + j * 32 + (lane & 31);
+    const float bias = p.bias[col];
+    const float qs = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * WTM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (row < M) {
+          float v = acc[i][j][r] * p.acc_scale + bias;
+          if (EPI == EPI_BIAS) {
+            v *= qs;
+          } else if (EPI == EPI_GELU) {
+            v = gelu_erf(v) * p.out_inv_scale;
+          } else {
+            v += ld((const TR*)p.resid + (size_t)row * N + col);
+          }
+          st(C + (size_t)row * N + col, v);
+        }
+      }
+    }
+  }
+}
+
+struct Cfg {
+  int bm, bn, bk;
+  const char* name;
+};
+
+// Tile configurations per input type; index = GemmParams::config.
+const Cfg kCfgBF16[] = {{128, 128, 64, "bf16_128x128x64_w2x2"},
+                        {256, 128, 64, "bf16_256x128x64_w2x2"},
+                        {128, 256, 64, "bf16_128x256x64_w2x2"},
+                        {256, 256, 32, "bf16_256x256x32_w2x2"}};
+const Cfg kCfgF32[] = {{128, 128, 32, "f32_128x128x32_w2x2"}, {64, 64, 32, "f32_64x64x32_w2x2"}};
+const Cfg kCfgFP8[] = {{128, 128, 128, "fp8_128x128x128_w2x2"}, {256, 128, 128, "fp8_256x128x128_w2x2"}};
+
+const Cfg* cfgs(ElemType t, int* n) {
+  if (t == ET_BF16) {
+    *n = 4;
+    return kCfgBF16;
+  }
+  if (t == ET_F32) {
+    *n = 2;
+    return kCfgF32;
+  }
+  *n = 2;
+  return kCfgFP8;
+}
+
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK>
+void run(const GemmParams& g, hipStream_t s) {
+  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale};
+  const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
+  hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, 2, 2>), dim3(tiles), dim3(256), 0, s, p);
+}
+
+template <typename TI, typename TO, typename TR, int EPI>
+bool dispatch_tile(const GemmParams& g, int ci, hipStream_t s) {
+  if constexpr (sizeof(TI) == 2) {
+    switch (ci) {
+      case 0: run<TI, TO, TR, EPI, 128, 128, 64>(g, s); return true;
+      case 1: run<TI, TO, TR, EPI, 256, 128, 64>(g, s); return true;
+      case 2: run<TI, TO, TR, EPI, 128, 256, 64>(g, s); return true;
+      case 3: run<TI, TO, TR, EPI, 256, 256, 32>(g, s); return true;
+    }
+  } else if constexpr (sizeof(TI) == 4) {
+    switch (ci) {
+      case 0: run<TI, TO, TR, EPI, 128, 128, 32>(g, s); return true;
+      case 1: run<TI, TO, TR, EPI, 64, 64, 32>(g, s); return true;
+    }
+  } else {
+    switch (ci) {
+      case 0: run<TI, TO, TR, EPI, 128, 128, 128>(g, s); return true;
+      case 1: run<TI, TO, TR, EPI, 256, 128, 128>(g, s); return true;
+    }
+  }
+  return false;
+}
+
+template <typename TI>
+bool dispatch_epi(const GemmParams& g, int ci, hipStream_t s) {
+  // Supported (epilogue, output, residual) combinations.
+  if (g.epi == EPI_BIAS) {
+    if (sizeof(TI) == 4 && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_BIAS>(g, ci, s);
+    if (sizeof(TI) != 4 && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_BIAS>(g, ci, s);
+  } else if (g.epi == EPI_GELU) {
+    if (sizeof(TI) == 4 && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GELU>(g, ci, s);
+    if (sizeof(TI) == 2 && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GELU>(g, ci, s);
+    if (sizeof(TI) == 1 && g.out == ET_FP8) return dispatch_tile<TI, fp8_t, float, EPI_GELU>(g, ci, s);
+  } else if (g.epi == EPI_RESID && g.out == ET_F32) {
+    if (sizeof(TI) == 4 && g.res == ET_F32) return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
+    if (sizeof(TI) != 4 && g.res == ET_BF16) return dispatch_tile<TI, float, bf16_t, EPI_RESID>(g, ci, s);
+  }
+  return false;
+}
+
+}  // namespace
+
+int gemm_num_configs(ElemType in) {
+  int n;
+  cfgs(in, &n);
+  return n;
+}
+
+const char* gemm_config_name(ElemType in, int config) {
+  int n;
+  const Cfg* c = cfgs(in, &n);
+  return (config >= 0 && config < n) ? c[config].name : "?";
+}
+
+bool gemm_config_fits(ElemType in, int config, int N, int K) {
+  int n;
+  const Cfg* c = cfgs(in, &n);
+  if (config < 0 || config >= n) return false;
+  return N % c[config].bn == 0 && K % c[config].bk == 0;
+}
+
+bool launch_gemm(const GemmParams& g, hipStream_t s) {
+  int ci = g.config;
+  if (ci < 0) {
+    // default: the preferred tile of the type if it divides the shape, else
+    // the first one that does
+    const int n = gemm_num_configs(g.in);
+    const int pref = g.in == ET_BF16 ? 1 : 0;
+    ci = gemm_config_fits(g.in, pref, g.N, g.K) ? pref : -1;
+    for (int c = 0; c < n && ci < 0; ++c)
+      if (gemm_config_fits(g.in, c, g.N, g.K)) ci = c;
+  }
+  if (ci < 0 || !gemm_config_fits(g.in, ci, g.N, g.K)) {
+    set_error(ANON_EINVAL, "gemm: no tile configuration divides N=" + std::to_string(g.N) + " K=" +
+                               std::to_string(g.K));
+    return false;
+  }
+  if (g.M <= 0) return true;
+  bool ok = false;
+  if (g.in == ET_F32) ok = dispatch_epi<float>(g, ci, s);
+  else if (g.in == ET_BF16) ok = dispatch_epi<bf16_t>(g, ci, s);
+  else ok = dispatch_epi<fp8_t>(g, ci, s);
+  if (!ok) set_error(ANON_EINVAL, "gemm: unsupported type/epilogue combination");
+  return ok;
+}
+
+}  // namespace anon

@@ -1,0 +1,280 @@
+// Row-wise kernels of the encoder: embedding + LayerNorm, LayerNorm, the
+// token-classification head (argmax and top-2 margin), type conversions and
+// the window gather / owner-window merge for long records.
+//
+// One 64-lane wave owns one token row; lane i holds elements i, i+64, ...
+// so every load and store is a contiguous 256-byte wave access.  LayerNorm
+// statistics are FP32 and two-pass (mean, then mean of squared deviations)
+// with a fixed butterfly reduction order, so a row's result never depends on
+// the other rows of the batch.
+#include "kernels.hpp"
+
+namespace anon {
+namespace {
+
+__device__ __forceinline__ float ldf(const float* p) { return *p; }
+__device__ __forceinline__ float ldf(const bf16_t* p) { return static_cast<float>(*p); }
+
+// Record containing packed token t (largest b with cu[b] <= t), robust to
+// malformed cu_seqlens (the result is then only clamped, never out of range).
+__device__ __forceinline__ int find_record(const int* cu, int B, int t) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cu[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NPL>
+__device__ __forceinline__ void ln_store(float (&v)[NPL], const float* g, const float* b, float eps, int h,
+                                         int lane, size_t row, void* out, ElemType out_t, fp8_t* out_q,
+                                         float q_inv_scale) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) s += v[i];
+  const float mean = wave_sum(s) / (float)h;
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const float d = v[i] - mean;
+    q += d * d;
+  }
+  const float var = wave_sum(q) / (float)h;
+  const float rstd = 1.0f / sqrtf(var + eps);
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int c = lane + 64 * i;
+    const float y = g[c] * ((v[i] - mean) * rstd) + b[c];
+    if (out_t == ET_F32) ((float*)out)[row * h + c] = y;
+    else {
+      const bf16_t yb = static_cast<bf16_t>(y);
+      ((bf16_t*)out)[row * h + c] = yb;
+      if (out_q) out_q[row * h + c].v = f32_to_e4m3(static_cast<float>(yb) * q_inv_scale);
+    }
+  }
+}
+
+template <int NPL>
+__global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ ids, const int* __restrict__ cu,
+                                                       int B, int T, const float* __restrict__ tok,
+                                                       const float* __restrict__ pos, const float* __restrict__ g,
+                                                       const float* __restrict__ b, float eps, int vocab,
+                                                       int max_pos, void* out, ElemType out_t, fp8_t* out_q,
+                                                       float q_inv_scale, uint32_t* err) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  constexpr int h = NPL * 64;
+  int id = ids[t];
+  if (id < 0 || id >= vocab) {
+    if (lane == 0) raise_error(err, ANON_ERR_TOKEN_ID);
+    id = 0;
+  }
+  const int r = find_record(cu, B, t);
+  const int p = min(max(t - cu[r], 0), max_pos - 1);
+  float v[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int c = lane + 64 * i;
+    v[i] = tok[(size_t)id * h + c] + pos[(size_t)p * h + c];
+  }
+  ln_store<NPL>(v, g, b, eps, h, lane, t, out, out_t, out_q, q_inv_scale);
+}
+
+template <int NPL>
+__global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict__ y, const float* __restrict__ g,
+                                                        const float* __restrict__ b, float eps, int rows, void* out,
+                                                        ElemType out_t, fp8_t* out_q, float q_inv_scale) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  constexpr int h = NPL * 64;
+  float v[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) v[i] = y[(size_t)row * h + lane + 64 * i];
+  ln_store<NPL>(v, g, b, eps, h, lane, row, out, out_t, out_q, q_inv_scale);
+}
+
+constexpr int kMaxLabels = 64;
+
+template <typename TX, int NPL>
+__global__ __launch_bounds__(256) void classifier_kernel(const TX* __restrict__ x, const float* __restrict__ wc,
+                                                         const float* __restrict__ bc, int T, int C,
+                                                         uint8_t* __restrict__ labels, float* __restrict__ logits,
+                                                         float* __restrict__ margin) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  constexpr int h = NPL * 64;
+  float xv[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) xv[i] = ldf(x + (size_t)t * h + lane + 64 * i);
+  float best = -INFINITY, second = -INFINITY, mine = 0.f;
+  int arg = 0;
+  for (int c = 0; c < C; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) s += xv[i] * wc[(size_t)c * h + lane + 64 * i];
+    const float z = wave_sum(s) + bc[c];
+    if (lane == c) mine = z;
+    if (z > best) {
+      second = best;
+      best = z;
+      arg = c;
+    } else if (z > second) {
+      second = z;
+    }
+  }
+  if (logits && lane < C) logits[(size_t)t * C + lane] = mine;
+  if (lane == 0) {
+    labels[t] = (uint8_t)arg;
+    if (margin) margin[t] = C > 1 ? best - second : INFINITY;
+  }
+}
+
+template <typename TX>
+__global__ void to_f32_kernel(const TX* __restrict__ x, float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ldf(x + i);
+}
+
+// dst[c][r] = src[r][c] * inv_scale, converted to the storage type.
+template <typename TD>
+__global__ __launch_bounds__(256) void transpose_convert_kernel(const float* __restrict__ src, int rows, int cols,
+                                                                TD* __restrict__ dst, float inv_scale) {
+  __shared__ float tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < rows && c < cols) ? src[(size_t)r * cols + c] : 0.f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < cols && r < rows) {
+      const float v = tile[tx][k] * inv_scale;
+      if constexpr (sizeof(TD) == 4) dst[(size_t)c * rows + r] = v;
+      else if constexpr (sizeof(TD) == 2) dst[(size_t)c * rows + r] = static_cast<bf16_t>(v);
+      else dst[(size_t)c * rows + r].v = f32_to_e4m3(v);
+    }
+  }
+}
+
+__global__ void window_gather_kernel(const int* __restrict__ ids, const int* __restrict__ cu,
+                                     const int4* __restrict__ win, int* __restrict__ w_ids) {
+  const int4 w = win[blockIdx.x];  // (record, start in record, length, first window token)
+  const int src = cu[w.x] + w.y;
+  for (int i = threadIdx.x; i < w.z; i += blockDim.x) w_ids[w.w + i] = ids[src + i];
+}
+
+__global__ void window_merge_kernel(const int* __restrict__ cu, int B, const int* __restrict__ rec_win0,
+                                    const int4* __restrict__ win, int window, int stride,
+                                    const uint8_t* __restrict__ wl, const float* __restrict__ wz,
+                                    const float* __restrict__ wm, int C, uint8_t* __restrict__ labels,
+                                    float* __restrict__ logits, float* __restrict__ margin, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const int b = find_record(cu, B, t);
+  const int i = t - cu[b];
+  const int nw = rec_win0[b + 1] - rec_win0[b];
+  const int half = (window - stride) / 2;
+  int k = i >= half ? (i - half) / stride : 0;
+  k = min(k, nw - 1);
+  const int4 w = win[rec_win0[b] + k];
+  const int src = w.w + (i - w.y);
+  labels[t] = wl[src];
+  if (margin) margin[t] = wm[src];
+  if (logits)
+    for (int c = 0; c < C; ++c) logits[(size_t)t * C + c] = wz[(size_t)src * C + c];
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+#define ANON_NPL_SWITCH(NPLV, ...)            \
+  switch (NPLV) {                             \
+    case 1: { constexpr int NPL = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int NPL = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int NPL = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int NPL = 8; __VA_ARGS__; } break;   \
+    case 12: { constexpr int NPL = 12; __VA_ARGS__; } break; \
+    case 16: { constexpr int NPL = 16; __VA_ARGS__; } break; \
+    default: break;                           \
+  }
+
+}  // namespace
+
+void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
+                     const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
+                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s) {
+  if (T <= 0) return;
+  ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((embed_ln_kernel<NPL>), dim3(ceil_div(T, 4)), dim3(256), 0, s, ids,
+                                             cu_seqlens, B, T, tok_emb, pos_emb, g, b, eps, vocab, max_pos, out,
+                                             out_t, out_q, q_inv_scale, err));
+}
+
+void launch_layernorm(const float* y, const float* g, const float* b, float eps, int rows, int h, void* out,
+                      ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
+  if (rows <= 0) return;
+  ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0, s, y, g,
+                                             b, eps, rows, out, out_t, out_q, q_inv_scale));
+}
+
+void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
+                       uint8_t* labels, float* logits, float* margin, hipStream_t s) {
+  if (T <= 0) return;
+  if (x_t == ET_F32) {
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((classifier_kernel<float, NPL>), dim3(ceil_div(T, 4)), dim3(256), 0,
+                                               s, (const float*)x, wc_t, bc, T, C, labels, logits, margin));
+  } else {
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((classifier_kernel<bf16_t, NPL>), dim3(ceil_div(T, 4)), dim3(256), 0,
+                                               s, (const bf16_t*)x, wc_t, bc, T, C, labels, logits, margin));
+  }
+}
+
+void launch_to_f32(const void* x, ElemType t, float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = ceil_div(n, 256);
+  if (t == ET_F32) hipLaunchKernelGGL(to_f32_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)x, out, n);
+  else hipLaunchKernelGGL(to_f32_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, (const bf16_t*)x, out, n);
+}
+
+void launch_transpose_convert(const float* src, int rows, int cols, void* dst, ElemType t, float inv_scale,
+                              hipStream_t s) {
+  dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32));
+  if (t == ET_F32)
+    hipLaunchKernelGGL(transpose_convert_kernel<float>, grid, dim3(256), 0, s, src, rows, cols, (float*)dst,
+                       inv_scale);
+  else if (t == ET_BF16)
+    hipLaunchKernelGGL(transpose_convert_kernel<bf16_t>, grid, dim3(256), 0, s, src, rows, cols, (bf16_t*)dst,
+                       inv_scale);
+  else
+    hipLaunchKernelGGL(transpose_convert_kernel<fp8_t>, grid, dim3(256), 0, s, src, rows, cols, (fp8_t*)dst,
+                       inv_scale);
+}
+
+void launch_window_gather(const int* ids, const int* cu_seqlens, const int4* windows, int n_windows, int* w_ids,
+                          hipStream_t s) {
+  if (n_windows <= 0) return;
+  hipLaunchKernelGGL(window_gather_kernel, dim3(n_windows), dim3(256), 0, s, ids, cu_seqlens, windows, w_ids);
+}
+
+void launch_window_merge(const int* cu_seqlens, int B, const int* rec_win0, const int4* windows, int window,
+                         int stride, const uint8_t* w_labels, const float* w_logits, const float* w_margin, int C,
+                         uint8_t* labels, float* logits, float* margin, int T, hipStream_t s) {
+  if (T <= 0) return;
+  hipLaunchKernelGGL(window_merge_kernel, dim3(ceil_div(T, 256)), dim3(256), 0, s, cu_seqlens, B, rec_win0, windows,
+                     window, stride, w_labels, w_logits, w_margin, C, labels, logits, margin, T);
+}
+
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_u8_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+}  // namespace anon

@@ -1,0 +1,103 @@
+// Host-side launchers of the gfx950 kernels (one translation unit each).
+#pragma once
+
+#include "common.hpp"
+
+namespace anon {
+
+// ---- GEMM: C[M,N] = A[M,K] * W[N,K]^T with a fused epilogue --------------
+enum GemmEpi { EPI_BIAS = 0, EPI_GELU = 1, EPI_RESID = 2 };
+enum ElemType { ET_F32 = 0, ET_BF16 = 1, ET_FP8 = 2 };
+
+struct GemmParams {
+  const void* A;      // [M, K] row-major, element type `in`
+  const void* W;      // [N, K] row-major (transposed weights), element type `in`
+  const float* bias;  // [N]
+  const void* resid;  // [M, N] (EPI_RESID), element type `res`
+  void* C;            // [M, N], element type `out`
+  int M, N, K;
+  float qscale;       // EPI_BIAS: columns n < qcols are multiplied by qscale
+  int qcols;
+  float acc_scale;    // multiplies the accumulator (FP8: sa * sw), else 1
+  float out_inv_scale;  // FP8 output: value / scale before rounding
+  ElemType in, out, res;
+  GemmEpi epi;
+  int config;         // tile configuration index (-1: default choice)
+};
+// Returns false (and sets the error) if no kernel matches the shapes/types.
+bool launch_gemm(const GemmParams& p, hipStream_t s);
+int gemm_num_configs(ElemType in);
+const char* gemm_config_name(ElemType in, int config);
+bool gemm_config_fits(ElemType in, int config, int N, int K);
+
+// ---- attention ------------------------------------------------------------
+// Builds the per-(record, q-block) work list from cu_seqlens.
+void launch_seq_plan(const int* cu_seqlens, int B, int T, int max_len, int bq, int4* qblocks, int max_q,
+                     int* n_qblocks, uint32_t* err, hipStream_t s);
+int attn_block_q(ElemType t);
+void launch_attention(const void* qkv, void* out, const int4* qblocks,
+                      const int* n_qblocks, int max_qblocks, int n_heads, int hidden, ElemType t, ElemType out_t,
+                      float out_inv_scale, hipStream_t s);
+
+// ---- row-wise kernels -----------------------------------------------------
+void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
+                     const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
+                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s);
+void launch_layernorm(const float* y, const float* g, const float* b, float eps, int rows, int h, void* out,
+                      ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s);
+void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
+                       uint8_t* labels, float* logits, float* margin, hipStream_t s);
+void launch_to_f32(const void* x, ElemType t, float* out, int64_t n, hipStream_t s);
+void launch_transpose_convert(const float* src, int rows, int cols, void* dst, ElemType t, float inv_scale,
+                              hipStream_t s);
+
+// ---- windows --------------------------------------------------------------
+void launch_window_gather(const int* ids, const int* cu_seqlens, const int4* windows, int n_windows,
+                          int* w_ids, hipStream_t s);
+void launch_window_merge(const int* cu_seqlens, int B, const int* rec_win0, const int4* windows, int window,
+                         int stride, const uint8_t* w_labels, const float* w_logits, const float* w_margin, int C,
+                         uint8_t* labels, float* logits, float* margin, int T, hipStream_t s);
+
+// ---- scans ----------------------------------------------------------------
+size_t scan_temp_bytes(int64_t n);
+// out[i] = sum_{j<i} in[i], i in [0, n]; out has n+1 entries.
+void launch_exclusive_scan_i32(const int* in, int* out, int64_t n, void* temp, hipStream_t s);
+void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* temp, hipStream_t s);
+
+// ---- spans ----------------------------------------------------------------
+void launch_bio_flags(const uint8_t* labels, const int* cu_seqlens, int B, int T, int n_types, int* flags,
+                      uint32_t* err, hipStream_t s);
+void launch_bio_write(const uint8_t* labels, const int* tok_off, const int* cu_seqlens, int B, int T, int n_types,
+                      const int* flags, const int* excl, anon_span* spans, int span_cap, int* cu_spans,
+                      uint32_t* err, hipStream_t s);
+
+// ---- pseudonyms -----------------------------------------------------------
+struct PcacheDev {
+  uint8_t* table;         // capacity entries
+  uint64_t mask;          // capacity - 1
+  uint32_t ipad[8], opad[8];  // SHA-256 states after the key blocks
+  int slug;
+  int n_types;
+  const uint8_t* names;   // concatenated type names
+  const int* name_off;    // [n_types + 1]
+  unsigned long long* counters;  // [0] lookups, [1] hits, [2] inserts
+  int enabled;
+};
+size_t pcache_entry_bytes();
+bool hmac_selftest();
+void sha256_hmac_midstates(const uint8_t* key, size_t key_len, uint32_t ipad[8], uint32_t opad[8]);
+void launch_ps_layout(const PcacheDev& pc, const int64_t* cu_bytes, int B, const anon_span* spans,
+                      const int* cu_spans, int span_cap, int64_t* out_len, int64_t* sp_out, int* sp_plen,
+                      int64_t* sp_in_end, uint32_t* err, hipStream_t s);
+void launch_ps_hash(const PcacheDev& pc, const uint8_t* text, const int64_t* cu_bytes, int B, const anon_span* spans,
+                    const int* cu_spans, int span_cap, const int* sp_plen, uint8_t* digests, hipStream_t s);
+void launch_ps_write(const PcacheDev& pc, const uint8_t* text, const int64_t* cu_bytes, int B,
+                     const anon_span* spans, const int* cu_spans, int span_cap, const int64_t* sp_out,
+                     const int* sp_plen, const int64_t* sp_in_end, const uint8_t* digests, const int64_t* cu_out,
+                     uint8_t* out, int64_t out_cap, uint32_t* err, hipStream_t s);
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+
+// Shape of a created model (the struct itself is private to the runtime).
+const anon_model_config* model_config(const anon_model* m);
+
+}  // namespace anon

@@ -1,0 +1,340 @@
+"""GPU path vs the FP64 oracle through the C ABI (needs an MI355X).
+
+Bars: FP32 logits within 1e-4 relative per token of the pure oracle; labels
+equal wherever the reference margin exceeds 1e-2 (pure oracle for FP32, the
+bf16-rounding oracle for BF16); spans, pseudonyms and substituted bytes
+bit-exact for integer work.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import encoder, pipeline as opipe, pseudonym as ops, spans as ospans
+from synth.configs import TINY, BASE, ModelConfig
+from tests.gpu_common import (MARGIN, FP32_LOGIT_RTOL, confident_labels_agree, confident_records, logit_rel_err,
+                              make_cache, make_model, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def tiny_batch():
+    return synth.generate_records(64, ("uniform", 16, 128), 4, TINY.vocab, 0)
+
+
+@pytest.fixture(scope="module")
+def tiny_fp32(torch_dev):
+    W, m = make_model(TINY, "fp32", 0)
+    return W, m
+
+
+def _run_ner(m, rb, logits=True, window=0, stride=0):
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+    db = DeviceBatch(rb)
+    pl = Pipeline(m)
+    lab, z, mg = pl.ner(db, logits=logits, margin=True, window=window, stride=stride)
+    import torch
+    torch.cuda.synchronize()
+    T = rb.n_tokens
+    return lab[:T].cpu().numpy(), (z[:T].cpu().numpy() if z is not None else None), mg[:T].cpu().numpy()
+
+
+def test_tiny_fp32_hidden_states_layer_by_layer(tiny_fp32, tiny_batch):
+    W, m = tiny_fp32
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+    db = DeviceBatch(tiny_batch)
+    pl = Pipeline(m)
+    for nl in range(TINY.n_layers + 1):
+        say(f"[tiny fp32] hidden after {nl} layers, T={tiny_batch.n_tokens}")
+        h = pl.hidden(db, nl)[: tiny_batch.n_tokens].cpu().numpy()
+        ref = encoder.hidden_states(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens, n_layers=nl)
+        err = np.abs(h - ref).max()
+        assert err < 2e-5 * max(1.0, np.abs(ref).max()), (nl, err)
+
+
+def test_tiny_fp32_logits_and_labels(tiny_fp32, tiny_batch):
+    W, m = tiny_fp32
+    say("[tiny fp32] ner_forward logits")
+    lab, z, mg = _run_ner(m, tiny_batch)
+    zr, lr, mr = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens)
+    rel = logit_rel_err(z, zr)
+    say(f"  max rel logit err {rel.max():.3e}")
+    assert rel.max() <= FP32_LOGIT_RTOL
+    bad, n = confident_labels_agree(lab, lr, mr)
+    assert len(bad) == 0 and n > 0.8 * len(lr)
+    np.testing.assert_allclose(mg, mr, atol=2e-5)
+
+
+def test_tiny_bf16_matches_rounding_oracle(torch_dev, tiny_batch):
+    W, m = make_model(TINY, "bf16", 0)
+    say("[tiny bf16] ner_forward vs bf16-rounding oracle")
+    lab, z, mg = _run_ner(m, tiny_batch)
+    zq, lq, mq = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens, encoder.Precision("bf16"))
+    zp, lp, mp = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens)
+    err_q = np.abs(z - zq).max()
+    err_p = np.abs(z - zp).max()
+    say(f"  max |z - z_bf16oracle| {err_q:.3e}   max |z - z_pure| {err_p:.3e}")
+    bad, n = confident_labels_agree(lab, lq, mq)
+    assert len(bad) == 0, (len(bad), n)
+    assert err_q < 5e-3
+
+
+def test_batch_invariance_alone_vs_packed(tiny_fp32, tiny_batch):
+    _, m = tiny_fp32
+    say("[tiny fp32] records alone vs packed")
+    lab, z, _ = _run_ner(m, tiny_batch)
+    for r in [0, 7, 33, 63]:
+        sub = tiny_batch.subset([r])
+        l1, z1, _ = _run_ner(m, sub)
+        a, b = tiny_batch.cu_seqlens[r], tiny_batch.cu_seqlens[r + 1]
+        np.testing.assert_array_equal(z1, z[a:b])
+        np.testing.assert_array_equal(l1, lab[a:b])
+
+
+def test_edge_lengths_one_token_and_max_pos(torch_dev):
+    cfg = ModelConfig(n_layers=2, hidden=128, n_heads=2, ffn=256, vocab=500, n_labels=9, max_pos=512)
+    W, m = make_model(cfg, "fp32", 3)
+    for lens in ([1], [512], [1, 512, 2, 129, 128, 127, 64, 65], [300, 1, 1, 1]):
+        say(f"[edge fp32] lengths {lens}")
+        rb = synth.generate_records(len(lens), np.array(lens), 4, cfg.vocab, 5)
+        lab, z, mg = _run_ner(m, rb)
+        zr, lr, mr = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens)
+        assert logit_rel_err(z, zr).max() <= FP32_LOGIT_RTOL
+
+
+def test_empty_batch_is_a_no_op(tiny_fp32):
+    import torch
+    from paper_2606_15650_amd import api
+    _, m = tiny_fp32
+    say("[empty] ner_forward with T=0")
+    cu = torch.zeros(1, dtype=torch.int32, device="cuda")
+    api.ner_forward(m, None, cu, 0, 0, None)
+    torch.cuda.synchronize()
+
+
+def test_out_of_range_token_id_is_flagged_not_faulting(tiny_fp32, tiny_batch):
+    import torch
+    from paper_2606_15650_amd import api
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+    _, m = tiny_fp32
+    say("[errors] token id >= vocab")
+    api.device_errors(0, clear=True)
+    rb = tiny_batch.subset([0, 1])
+    rb.ids = rb.ids.copy()
+    rb.ids[3] = TINY.vocab + 100
+    db = DeviceBatch(rb)
+    Pipeline(m).ner(db)
+    torch.cuda.synchronize()
+    assert api.device_errors(0, clear=True) & api.ERR_TOKEN_ID
+
+
+def test_windowed_ner_matches_oracle(tiny_fp32):
+    W, m = tiny_fp32
+    rb = synth.generate_records(5, np.array([40, 200, 130, 64, 65]), 4, TINY.vocab, 9)
+    for win, st in ((64, 48), (128, 96)):
+        say(f"[tiny fp32] windowed ner window={win} stride={st}")
+        lab, z, mg = _run_ner(m, rb, window=win, stride=st)
+        zr, lr, mr = opipe.ner(W, TINY, rb.ids, rb.cu_seqlens, window=win, stride=st)
+        assert logit_rel_err(z, zr).max() <= FP32_LOGIT_RTOL
+        bad, _ = confident_labels_agree(lab, lr, mr)
+        assert len(bad) == 0
+
+
+def _decode_gpu(rb, labels, n_types, span_cap=None):
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, spans_to_numpy
+    from paper_2606_15650_amd import api
+    db = DeviceBatch(rb)
+    cap = rb.n_tokens if span_cap is None else span_cap
+    lab = torch.from_numpy(np.ascontiguousarray(labels, np.uint8)).cuda()
+    spans = torch.empty((max(cap, 1), 3), dtype=torch.int64, device="cuda")
+    cu_spans = torch.empty(rb.n_records + 1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(api.decode_workspace_size(rb.n_tokens, rb.n_records), dtype=torch.uint8, device="cuda")
+    api.decode_spans(lab, db.tok_off, db.cu, rb.n_records, rb.n_tokens, n_types, spans, cap, cu_spans, ws, ws.numel())
+    torch.cuda.synchronize()
+    cs = cu_spans.cpu().numpy()
+    return spans_to_numpy(spans, min(int(cs[-1]), cap)), cs
+
+
+@pytest.mark.parametrize("kind", ["gold", "random", "all_entity"])
+def test_decode_spans_bit_exact(torch_dev, kind):
+    rb = synth.generate_records(200, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 21)
+    rng = np.random.default_rng(4)
+    if kind == "gold":
+        lab = rb.gold_labels
+    elif kind == "random":
+        lab = rng.integers(0, 17, rb.n_tokens).astype(np.uint8)
+    else:
+        lab = rng.integers(1, 17, rb.n_tokens).astype(np.uint8)
+    say(f"[decode] {kind} labels, T={rb.n_tokens}")
+    got, cs = _decode_gpu(rb, lab, 8)
+    want = ospans.bio_decode(lab, rb.tok_off, rb.cu_seqlens, 8)
+    np.testing.assert_array_equal(got, want)
+    assert cs[-1] == len(want)
+    if kind == "gold":
+        np.testing.assert_array_equal(got, rb.gold_spans)
+
+
+def test_decode_span_capacity_reports_total(torch_dev):
+    rb = synth.generate_records(20, ("uniform", 16, 64), 4, 8192, 2)
+    lab = np.ones(rb.n_tokens, np.uint8)  # every token a B- label
+    say("[decode] span_cap smaller than the span count")
+    got, cs = _decode_gpu(rb, lab, 4, span_cap=10)
+    assert cs[-1] == rb.n_tokens and len(got) == 10
+
+
+def _pseudo_gpu(rb, spans, cache, B=None):
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list
+    from paper_2606_15650_amd import api
+    db = DeviceBatch(rb)
+    n = len(spans)
+    cap = max(n, 1)
+    raw = np.zeros((cap, 3), np.int64)
+    if n:
+        raw[:n, 0] = (spans[:, 0] & 0xFFFFFFFF) | (spans[:, 1] << 32)
+        raw[:n, 1] = spans[:, 2]
+        raw[:n, 2] = spans[:, 3]
+    d_sp = torch.from_numpy(raw).cuda()
+    counts = np.bincount(spans[:, 0], minlength=rb.n_records) if n else np.zeros(rb.n_records, np.int64)
+    cu_spans = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)).cuda()
+    pl = Pipeline.__new__(Pipeline)
+    pl.cache, pl.device, pl._ws = cache, torch.device("cuda:0"), {}
+    out, cu_out = pl.pseudonymize(db, d_sp, cu_spans, cap)
+    torch.cuda.synchronize()
+    return outputs_to_list(out, cu_out)
+
+
+@pytest.mark.parametrize("slug", [0, 10, 64])
+def test_pseudonymize_bit_exact_on_gold_spans(torch_dev, slug):
+    rb = synth.generate_records(300, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 31)
+    cache = make_cache(rb.type_names, slug=slug)
+    key = synth.make_key(0)
+    say(f"[pseudonymize] gold spans, slug={slug}, spans={len(rb.gold_spans)}")
+    got = _pseudo_gpu(rb, rb.gold_spans, cache)
+    want = ops.pseudonymize_batch(rb.text, rb.cu_bytes, rb.gold_spans, rb.n_records, rb.type_names, key, slug)
+    assert got == want
+    # second call: served from the table, same bytes (cache on/off invariance)
+    got2 = _pseudo_gpu(rb, rb.gold_spans, cache)
+    assert got2 == want
+    st = cache.stats()
+    if slug:
+        assert st["hits"] > 0 and st["entries"] > 0
+    cache.set_enabled(False)
+    assert _pseudo_gpu(rb, rb.gold_spans, cache) == want
+
+
+def test_hmac_block_edges(torch_dev):
+    """Entity lengths around the SHA-256 padding and block edges, and past the table limit."""
+    lens = [0, 1, 2, 31, 32, 55, 56, 57, 63, 64, 65, 96, 97, 119, 120, 128, 200, 300]
+    rng = np.random.default_rng(0)
+    parts, spans, pos = [], [], 0
+    for L in lens:
+        e = bytes(rng.integers(33, 127, L).astype(np.uint8))
+        parts.append(b"x " + e + b" ")
+        spans.append((0, 1, pos + 2, pos + 2 + L))
+        pos += L + 3
+    text = b"".join(parts)
+    rb = synth.records.RecordBatch(text, np.array([0, len(text)]), np.zeros(1, np.int32), np.zeros((1, 2), np.int32),
+                                   np.array([0, 1], np.int32), np.zeros(1, np.uint8), np.zeros((0, 4)), ["HASH"])
+    sp = np.array(spans, np.int64)
+    key = b"\x0b" * 20
+    for slug in (64, 7):
+        from paper_2606_15650_amd import api
+        cache = api.PseudonymCache(key, slug, ["HASH"], 4096)
+        say(f"[hmac] {len(lens)} entity lengths, slug={slug}")
+        got = _pseudo_gpu(rb, sp, cache)
+        want = ops.pseudonymize_batch(text, [0, len(text)], sp, 1, ["HASH"], key, slug)
+        assert got == want
+
+
+def test_long_key_is_hashed_first(torch_dev):
+    from paper_2606_15650_amd import api
+    key = bytes(range(200))
+    text = b"host 10.1.2.3 and web01.corp"
+    rb = synth.records.RecordBatch(text, np.array([0, len(text)]), np.zeros(1, np.int32), np.zeros((1, 2), np.int32),
+                                   np.array([0, 1], np.int32), np.zeros(1, np.uint8), np.zeros((0, 4)),
+                                   ["IP_ADDRESS", "HOSTNAME"])
+    sp = np.array([[0, 1, 5, 13], [0, 2, 18, 28]], np.int64)
+    cache = api.PseudonymCache(key, 12, ["IP_ADDRESS", "HOSTNAME"], 1024)
+    say("[hmac] 200-byte key")
+    got = _pseudo_gpu(rb, sp, cache)
+    want = ops.pseudonymize_batch(text, [0, len(text)], sp, 1, ["IP_ADDRESS", "HOSTNAME"], key, 12)
+    assert got == want
+
+
+def test_bad_spans_are_skipped_and_flagged(torch_dev):
+    from paper_2606_15650_amd import api
+    text = b"aaaa bbbb cccc"
+    rb = synth.records.RecordBatch(text, np.array([0, len(text)]), np.zeros(1, np.int32), np.zeros((1, 2), np.int32),
+                                   np.array([0, 1], np.int32), np.zeros(1, np.uint8), np.zeros((0, 4)), ["T"])
+    # second span overlaps the first, third runs past the record: both skipped
+    sp = np.array([[0, 1, 0, 4], [0, 1, 2, 6], [0, 1, 10, 99]], np.int64)
+    cache = api.PseudonymCache(b"k", 4, ["T"], 1024)
+    api.device_errors(0, clear=True)
+    say("[pseudonymize] malformed spans")
+    got = _pseudo_gpu(rb, sp, cache)
+    want = ops.pseudonymize_batch(text, [0, len(text)], sp[:1], 1, ["T"], b"k", 4)
+    assert got == want
+    assert api.device_errors(0, clear=True) & api.ERR_SPAN
+
+
+def test_full_path_tiny_fp32_matches_oracle(tiny_fp32, tiny_batch):
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list, spans_to_numpy
+    W, m = tiny_fp32
+    cache = make_cache(tiny_batch.type_names)
+    key = synth.make_key(0)
+    say("[tiny fp32] whole path: ner -> spans -> pseudonyms")
+    db = DeviceBatch(tiny_batch)
+    pl = Pipeline(m, cache)
+    labels, spans, cu_spans, out, cu_out = pl.step(db)
+    torch.cuda.synchronize()
+    outs = outputs_to_list(out, cu_out)
+    res = opipe.run(W, TINY, tiny_batch, key, 10)
+    conf = confident_records(res.margin, tiny_batch.cu_seqlens)
+    assert len(conf) > 0
+    for r in conf:
+        assert outs[r] == res.outputs[r]
+    # the integer tail is exact given the GPU's own labels
+    lab = labels[: tiny_batch.n_tokens].cpu().numpy()
+    res_g = opipe.run(W, TINY, tiny_batch, key, 10, labels_override=lab)
+    assert outs == res_g.outputs
+    cs = cu_spans.cpu().numpy()
+    np.testing.assert_array_equal(spans_to_numpy(spans, int(cs[-1])), res_g.spans)
+
+
+def test_base_bf16_small_batch_vs_rounding_oracle(torch_dev):
+    """12-layer h768 encoder, a few records (incl. 512 tokens), BF16 vs the bf16 oracle."""
+    rb = synth.generate_records(6, np.array([512, 37, 200, 16, 129, 300]), 8, BASE.vocab, 17)
+    W, m = make_model(BASE, "bf16", 0, o_target=0.92)
+    say(f"[base bf16] T={rb.n_tokens}")
+    lab, z, mg = _run_ner(m, rb)
+    zq, lq, mq = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens, encoder.Precision("bf16"))
+    zp, lp, mp = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens)
+    say(f"  max |z-zq| {np.abs(z - zq).max():.3e}  max |z-zpure| {np.abs(z - zp).max():.3e}  "
+        f"O-rate {(lab == 0).mean():.3f}")
+    bad, n = confident_labels_agree(lab, lq, mq)
+    assert len(bad) == 0, (len(bad), n)
+    m.close()
+
+
+def test_base_fp32_small_batch_vs_pure_oracle(torch_dev):
+    rb = synth.generate_records(4, np.array([512, 100, 17, 250]), 8, BASE.vocab, 18)
+    W, m = make_model(BASE, "fp32", 0, o_target=0.92)
+    say(f"[base fp32] T={rb.n_tokens}")
+    lab, z, mg = _run_ner(m, rb)
+    zr, lr, mr = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens)
+    rel = logit_rel_err(z, zr)
+    say(f"  max rel logit err {rel.max():.3e}")
+    assert rel.max() <= FP32_LOGIT_RTOL
+    bad, _ = confident_labels_agree(lab, lr, mr)
+    assert len(bad) == 0
+    m.close()

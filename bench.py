@@ -1,0 +1,203 @@
+"""Throughput of the NER + pseudonymize path on one MI355X.
+
+A step is one pass of the whole path over one resident batch: ner_forward
+(embedding, 12 post-LN encoder layers, classifier), decode_spans and
+pseudonymize, all on one stream.  Inputs (token ids, offsets, text) are in HBM
+before the timed region starts.
+
+    python bench.py [--steps K] [--warmup W] [--workload base_bf16]
+
+Prints one JSON line.  Besides the headline tokens/s it reports the plain FP32
+path on the same batch (the speedup baseline), per-step p50/p99 latency, the
+dominant kernel against the MFMA roofline (timed with HIP events on its launch
+stream during the timed steps), and the FP64 oracle's throughput on a bounded
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks (dense): FLOP/s per operand type, HBM bytes/s
+PEAK_FLOPS = {"bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12}
+PEAK_HBM = 8.0e12
+
+
+def attention_flops(cu: np.ndarray, cfg) -> float:
+    """Algorithmic attention FLOPs of one layer: QK^T and PV over each record."""
+    L = np.diff(cu).astype(np.float64)
+    return float((4.0 * L * L * cfg.hidden).sum())
+
+
+def gemm_flops_per_token(cfg) -> dict:
+    h, f = cfg.hidden, cfg.ffn
+    return {"qkv": 2 * h * 3 * h, "oproj": 2 * h * h, "ffn1": 2 * h * f, "ffn2": 2 * f * h}
+
+
+def path_flops(cfg, cu: np.ndarray) -> float:
+    T = float(cu[-1])
+    g = sum(gemm_flops_per_token(cfg).values())
+    return cfg.n_layers * (g * T + attention_flops(cu, cfg)) + 2.0 * cfg.hidden * cfg.n_labels * T
+
+
+def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
+    """The FP64 oracle on the first records of the workload, until ~budget_s of CPU work."""
+    from oracle import pipeline as opipe
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    tok = 0
+    nrec = 0
+    t0 = time.perf_counter()
+    step = 2
+    while nrec < rb.n_records and time.perf_counter() - t0 < budget_s:
+        sub = rb.subset(range(nrec, min(nrec + step, rb.n_records)))
+        opipe.run(W, wl.model, sub, key, 10)
+        tok += sub.n_tokens
+        nrec += sub.n_records
+    dt = time.perf_counter() - t0
+    return {"value": tok / dt, "unit": "tokens/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {nrec} records ({tok} tokens) of the {wl.name} workload through the FP64 oracle "
+                      f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="base_bf16")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(records shard across GPUs without communication, see DESIGN.md)"}))
+        return 2
+
+    import torch
+
+    import synth
+    from paper_2606_15650_amd import api
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+
+    wl = synth.workload(a.workload)
+    cfg = wl.model
+    t_gen = time.perf_counter()
+    rb = synth.generate_records(wl.n_records, wl.lengths, cfg.n_types, cfg.vocab, wl.seed)
+    W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
+    key = synth.make_key(0)
+    blob = synth.weights_blob(cfg, W)
+    gen_s = time.perf_counter() - t_gen
+    T, B = rb.n_tokens, rb.n_records
+    cu = rb.cu_seqlens.astype(np.int64)
+
+    def run_path(precision: str, steps: int, warmup: int, prof: bool):
+        model = api.Model(cfg, blob, precision)
+        cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
+        pl = Pipeline(model, cache)
+        db = DeviceBatch(rb)
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            pl.step(db)
+        torch.cuda.synchronize()
+        classes = ["qkv", "attn", "oproj", "ffn1", "ffn2", "ln", "embed", "cls"]
+        if prof:
+            for k in classes:
+                api.prof_enable(k, True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(steps):
+            pl.step(db)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        kern = {}
+        if prof:
+            for k in classes:
+                kern[k] = api.prof_read(k)
+                api.prof_enable(k, False)
+        st = cache.stats()
+        n_spans = None
+        model.close()
+        cache.close()
+        return wall, per, kern, st
+
+    wall, per, kern, cstats = run_path(wl.precision, a.steps, a.warmup, prof=True)
+    tokens_per_s = T * a.steps / wall
+    # dominant kernel class (largest total time) against its roofline
+    gemm_tok = gemm_flops_per_token(cfg)
+    total_att = attention_flops(cu, cfg)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    if dom in gemm_tok:
+        flops_per_launch = gemm_tok[dom] * T
+        bound, peak, unit = "mfma", PEAK_FLOPS[wl.precision], "TFLOP/s"
+    elif dom == "attn":
+        flops_per_launch = total_att
+        bound, peak, unit = "mfma", PEAK_FLOPS["bf16" if wl.precision != "fp32" else "fp32"], "TFLOP/s"
+    else:
+        flops_per_launch = None
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) if flops_per_launch else None
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
+                "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms,
+                "flops_per_launch": flops_per_launch}
+    breakdown = {}
+    for k, v in kern.items():
+        if v["launches"]:
+            f = gemm_tok[k] * T * v["launches"] if k in gemm_tok else (total_att * v["launches"] if k == "attn" else 0)
+            breakdown[k] = {"launches": v["launches"], "ms_per_step": v["ms"] / a.steps,
+                            "tflops": (f / (v["ms"] * 1e-3) / 1e12) if f else None}
+    flops = path_flops(cfg, cu)
+    out = {
+        "metric": "NER+pseudonymize tokens/sec/GPU",
+        "value": tokens_per_s,
+        "unit": "tokens/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.precision,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "records": B, "tokens": T, "layers": cfg.n_layers, "hidden": cfg.hidden,
+                   "heads": cfg.n_heads, "ffn": cfg.ffn, "vocab": cfg.vocab, "labels": cfg.n_labels,
+                   "lengths": list(wl.lengths), "packing": "varlen, no padding", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "path_tflops": flops / (wall / a.steps) / 1e12,
+        "path_mfma_frac": flops / (wall / a.steps) / PEAK_FLOPS[wl.precision],
+        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                            "mean": float(per.mean())},
+        "kernels": breakdown,
+        "pcache": cstats,
+        "input_gen_s": gen_s,
+    }
+    if not a.no_fp32 and wl.precision != "fp32":
+        w32, per32, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
+        tps32 = T * max(2, a.steps // 4) / w32
+        out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, rb, W, key, a.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -132,6 +132,7 @@ def encoder_layer(W, cfg, l: int, x: np.ndarray, cu_seqlens: np.ndarray, prec: P
     h, H = cfg.hidden, cfg.n_heads
     d = h // H
     p = f"l{l}."
+    x_in = x
     qkv = prec.gemm_in(x, l, 0) @ prec.gemm_w(_w(W, p + "wqkv")) + _w(W, p + "bqkv")
     qkv = prec.store(qkv)
     A = np.empty((x.shape[0], h))
@@ -147,11 +148,12 @@ def encoder_layer(W, cfg, l: int, x: np.ndarray, cu_seqlens: np.ndarray, prec: P
     A = prec.store(A)
     y = x + prec.gemm_in(A, l, 1) @ prec.gemm_w(_w(W, p + "wo")) + _w(W, p + "bo")
     x = prec.store(layer_norm(y, _w(W, p + "ln1_g"), _w(W, p + "ln1_b"), cfg.ln_eps))
+    x_mid = x
     g = prec.store(gelu(prec.gemm_in(x, l, 2) @ prec.gemm_w(_w(W, p + "w1")) + _w(W, p + "b1")))
     y = x + prec.gemm_in(g, l, 3) @ prec.gemm_w(_w(W, p + "w2")) + _w(W, p + "b2")
     x = prec.store(layer_norm(y, _w(W, p + "ln2_g"), _w(W, p + "ln2_b"), cfg.ln_eps))
     if taps is not None:
-        taps[l] = dict(qkv=qkv, attn=A, ffn1=g)
+        taps[l] = dict(qkv=qkv, attn=A, ffn1=g, x_in=x_in, x_mid=x_mid)
     return x
 
 

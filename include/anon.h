@@ -129,6 +129,24 @@ anon_status ner_forward(anon_model* model, const int32_t* d_ids, const int32_t* 
                         int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
                         size_t ws_bytes, void* stream);
 
+/* GEMM tile autotuner.  Times every tile configuration that fits each of the
+ * four encoder GEMMs (0 QKV, 1 output projection, 2 FFN1, 3 FFN2) on T rows,
+ * using d_workspace (>= anon_ner_workspace_size(T, 1) bytes; overwritten) as
+ * operand memory, and keeps the fastest for this model's later calls.  All
+ * configurations of a precision form every output element with the same
+ * MFMA sequence in the same K order, so tuning never changes results.
+ *   chosen:   [4] picked configuration per GEMM, or NULL
+ *   times_ms: [4 * max_configs] mean time per configuration (-1: does not
+ *             fit the shape), or NULL
+ * Synchronises the stream. */
+anon_status anon_autotune(anon_model* model, int32_t T, void* d_workspace, size_t ws_bytes, void* stream,
+                          int32_t* chosen, float* times_ms, int32_t max_configs);
+/* Set the tile configuration of each encoder GEMM (-1 = built-in default). */
+anon_status anon_model_set_tiles(anon_model* model, const int32_t tiles[4]);
+/* Number of tile configurations of a precision and the name of one. */
+int32_t anon_tile_config_count(anon_precision precision);
+const char* anon_tile_config_name(anon_precision precision, int32_t config);
+
 /* Hidden state after the first n_layers layers (0 = after the embedding
  * LayerNorm) as FP32 [T, hidden] in d_hidden: the activations ner_forward
  * computes, exposed for layer-by-layer checking.  Same workspace rule. */

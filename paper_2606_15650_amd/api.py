@@ -87,6 +87,10 @@ _SIGS = {
     "anon_poll": ([vp, u64, C.POINTER(ResultC)], i32),
     "anon_release": ([vp, u64], i32),
     "anon_server_stop": ([vp], i32),
+    "anon_autotune": ([vp, i32, vp, sz, vp, C.POINTER(i32), C.POINTER(C.c_float), i32], i32),
+    "anon_model_set_tiles": ([vp, C.POINTER(i32)], i32),
+    "anon_tile_config_count": ([i32], i32),
+    "anon_tile_config_name": ([i32, i32], C.c_char_p),
     "anon_prof_enable": ([i32, i32], i32),
     "anon_prof_read": ([i32, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
 }
@@ -164,6 +168,23 @@ class Model:
                lib().anon_ner_windowed_workspace_size(self.handle, cu.ctypes.data, cu.size - 1, window, stride,
                                                       C.byref(n)))
         return n.value
+
+    def tile_configs(self) -> list[str]:
+        p = PRECISION[self.precision]
+        return [lib().anon_tile_config_name(p, i).decode() for i in range(lib().anon_tile_config_count(p))]
+
+    def autotune(self, T: int, d_workspace, ws_bytes: int, stream=None):
+        """Pick the fastest GEMM tiles on T rows; returns (chosen[4], times_ms[4][n])."""
+        n = len(self.tile_configs())
+        chosen = (i32 * 4)()
+        times = (C.c_float * (4 * n))()
+        _check("anon_autotune", lib().anon_autotune(self.handle, T, ptr(d_workspace), ws_bytes,
+                                                    stream_handle(stream), chosen, times, n))
+        return list(chosen), np.array(times[:], dtype=np.float32).reshape(4, n)
+
+    def set_tiles(self, tiles):
+        t = (i32 * 4)(*[int(x) for x in tiles])
+        _check("anon_model_set_tiles", lib().anon_model_set_tiles(self.handle, t))
 
     def close(self):
         if getattr(self, "handle", None):

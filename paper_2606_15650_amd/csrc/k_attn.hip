@@ -186,13 +186,19 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
   }
   if (active) {
     const float ltot = lsum + __shfl_xor(lsum, 32, 64);
-    const float inv = out_inv_scale / ltot;
+    const float inv = 1.0f / ltot;
     if (qrow < L) {
       TO* dst = out + (size_t)(base + qrow) * hidden + head * D;
 #pragma unroll
       for (int db = 0; db < 2; ++db)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), o[db][r] * inv);
+        for (int r = 0; r < 16; ++r) {
+          float v = o[db][r] * inv;
+          // FP8 output: round to bf16 (the stored attention output), then
+          // scale and round to E4M3
+          if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * out_inv_scale;
+          st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), v);
+        }
     }
   }
 }

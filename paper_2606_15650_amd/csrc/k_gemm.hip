@@ -7,11 +7,16 @@
 //   fp32: v_mfma_f32_32x32x2_f32      (K step 2)
 //   bf16: v_mfma_f32_32x32x16_bf16    (K step 16)
 //   fp8 : v_mfma_scale_f32_32x32x64_f8f6f4 with E4M3 operands (K step 64)
-// A and W tiles are staged through double-buffered, row-padded LDS; the next
-// K tile is fetched into registers while the current one is multiplied.
+// A and W tiles are staged through double-buffered, row-padded LDS (16 bytes
+// of padding per row keeps the 16-byte fragment reads of 16 lanes on distinct
+// banks).  The next K tile is fetched into registers while the current one is
+// multiplied, and the MFMA operands of k-step s+1 are read from LDS while the
+// MFMAs of step s run.
+//
 // The K loop always runs in increasing k with one MFMA shape per precision,
 // so each output element's sum is formed in the same order whatever the tile
-// shape or the row's position in the batch (batch invariance).
+// shape or the row's position in the batch (batch invariance; tile
+// configurations are interchangeable bit for bit).
 //
 // Epilogues: bias (+ exact scaling of the Q columns by 1/sqrt(d)); bias + GELU;
 // bias + residual into an FP32 pre-LayerNorm buffer.
@@ -57,7 +62,20 @@ __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 __device__ __forceinline__ void st(bf16_t* p, float v) { *p = static_cast<bf16_t>(v); }
 __device__ __forceinline__ void st(fp8_t* p, float v) { p->v = f32_to_e4m3(v); }
 
-__device__ __forceinline__ float gelu_erf(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+// GELU(v) = v/2 (1 + erf(v / sqrt 2)) with erf from Abramowitz & Stegun
+// formula 7.1.26 (rational approximation, |error| <= 1.5e-7): far below the
+// bf16 output rounding and the FP32 path's 1e-4 logit tolerance, and a third
+// of the instructions of a full-precision erff in an epilogue that runs
+// once per output element.
+__device__ __forceinline__ float gelu_erf(float v) {
+  const float x = v * 0.70710678118654752f;
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = ((((1.061405429f * t - 1.453152027f) * t + 1.421413741f) * t - 0.284496736f) * t +
+                      0.254829592f) * t;
+  const float e = 1.0f - poly * __expf(-ax * ax);
+  return 0.5f * v * (1.0f + copysignf(e, x));
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous run of tiles so that the tiles sharing an A row-block (and the
@@ -82,8 +100,8 @@ struct DevParams {
   float out_inv_scale;
 };
 
-template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN>
-__global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int OCC>
+__global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   typedef Mfma<TI> MF;
   typedef typename MF::frag frag;
   constexpr int NT = WGM * WGN * 64;
@@ -93,6 +111,7 @@ __global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
   constexpr int CPR = BK / EPC;              // chunks per tile row
   constexpr int LDK = BK + EPC;              // padded LDS row (16 bytes)
   constexpr int A_CH = BM * CPR / NT, B_CH = BN * CPR / NT;
+  constexpr int NKS = BK / MF::KI;
   static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "tile/threads mismatch");
   static_assert(TM >= 1 && TN >= 1 && BK % MF::KI == 0, "bad tile");
 
@@ -157,17 +176,28 @@ __global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
   for (int kt = 0; kt < KT; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < KT) gload((kt + 1) * BK);
+    const TI* as = As[buf];
+    const TI* bs = Bs[buf];
+    frag a[2][TM], b[2][TN];
 #pragma unroll
-    for (int ks = 0; ks < BK / MF::KI; ++ks) {
-      frag a[TM], b[TN];
+    for (int i = 0; i < TM; ++i) a[0][i] = *(const frag*)&as[(arow + i * 32) * LDK + kofs];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = *(const frag*)&As[buf][(arow + i * 32) * LDK + ks * MF::KI + kofs];
+    for (int j = 0; j < TN; ++j) b[0][j] = *(const frag*)&bs[(brow + j * 32) * LDK + kofs];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = *(const frag*)&Bs[buf][(brow + j * 32) * LDK + ks * MF::KI + kofs];
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < NKS) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          a[cur ^ 1][i] = *(const frag*)&as[(arow + i * 32) * LDK + (ks + 1) * MF::KI + kofs];
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          b[cur ^ 1][j] = *(const frag*)&bs[(brow + j * 32) * LDK + (ks + 1) * MF::KI + kofs];
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[cur][i], b[cur][j], acc[i][j]);
     }
     if (kt + 1 < KT) lstore(buf ^ 1);
     __syncthreads();
@@ -191,7 +221,10 @@ __global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
           if (EPI == EPI_BIAS) {
             v *= qs;
           } else if (EPI == EPI_GELU) {
-            v = gelu_erf(v) * p.out_inv_scale;
+            v = gelu_erf(v);
+            // FP8 output: the activation is a bf16 value first (as in the
+            // BF16 path), then scaled and rounded to E4M3
+            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
           } else {
             v += ld((const TR*)p.resid + (size_t)row * N + col);
           }
@@ -203,57 +236,73 @@ __global__ __launch_bounds__(WGM* WGN * 64) void gemm_kernel(DevParams p) {
 }
 
 struct Cfg {
-  int bm, bn, bk;
+  int bm, bn, bk, wgm, wgn, occ;
   const char* name;
 };
 
 // Tile configurations per input type; index = GemmParams::config.
-const Cfg kCfgBF16[] = {{128, 128, 64, "bf16_128x128x64_w2x2"},
-                        {256, 128, 64, "bf16_256x128x64_w2x2"},
-                        {128, 256, 64, "bf16_128x256x64_w2x2"},
-                        {256, 256, 32, "bf16_256x256x32_w2x2"}};
-const Cfg kCfgF32[] = {{128, 128, 32, "f32_128x128x32_w2x2"}, {64, 64, 32, "f32_64x64x32_w2x2"}};
-const Cfg kCfgFP8[] = {{128, 128, 128, "fp8_128x128x128_w2x2"}, {256, 128, 128, "fp8_256x128x128_w2x2"}};
+#define ANON_BF16_CFGS(X)                          \
+  X(0, 128, 128, 64, 2, 2, 2, "bf16_128x128x64_w2x2") \
+  X(1, 256, 128, 64, 2, 2, 1, "bf16_256x128x64_w2x2") \
+  X(2, 128, 256, 64, 2, 2, 1, "bf16_128x256x64_w2x2") \
+  X(3, 256, 256, 32, 2, 2, 1, "bf16_256x256x32_w2x2") \
+  X(4, 256, 256, 64, 2, 2, 1, "bf16_256x256x64_w2x2") \
+  X(5, 256, 128, 32, 2, 2, 2, "bf16_256x128x32_w2x2") \
+  X(6, 128, 256, 32, 2, 2, 2, "bf16_128x256x32_w2x2") \
+  X(7, 256, 256, 64, 4, 2, 2, "bf16_256x256x64_w4x2") \
+  X(8, 256, 256, 32, 4, 2, 2, "bf16_256x256x32_w4x2") \
+  X(9, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2")
+#define ANON_F32_CFGS(X)                         \
+  X(0, 128, 128, 32, 2, 2, 2, "f32_128x128x32_w2x2") \
+  X(1, 64, 64, 32, 2, 2, 2, "f32_64x64x32_w2x2")     \
+  X(2, 128, 128, 16, 2, 2, 2, "f32_128x128x16_w2x2") \
+  X(3, 256, 128, 16, 2, 2, 1, "f32_256x128x16_w2x2")
+#define ANON_FP8_CFGS(X)                           \
+  X(0, 128, 128, 128, 2, 2, 2, "fp8_128x128x128_w2x2") \
+  X(1, 256, 128, 128, 2, 2, 1, "fp8_256x128x128_w2x2") \
+  X(2, 256, 256, 64, 2, 2, 1, "fp8_256x256x64_w2x2")   \
+  X(3, 128, 256, 128, 2, 2, 1, "fp8_128x256x128_w2x2") \
+  X(4, 256, 128, 64, 2, 2, 2, "fp8_256x128x64_w2x2")
+
+#define ANON_CFG_ROW(i, bm, bn, bk, wgm, wgn, occ, name) {bm, bn, bk, wgm, wgn, occ, name},
+const Cfg kCfgBF16[] = {ANON_BF16_CFGS(ANON_CFG_ROW)};
+const Cfg kCfgF32[] = {ANON_F32_CFGS(ANON_CFG_ROW)};
+const Cfg kCfgFP8[] = {ANON_FP8_CFGS(ANON_CFG_ROW)};
 
 const Cfg* cfgs(ElemType t, int* n) {
   if (t == ET_BF16) {
-    *n = 4;
+    *n = (int)(sizeof(kCfgBF16) / sizeof(Cfg));
     return kCfgBF16;
   }
   if (t == ET_F32) {
-    *n = 2;
+    *n = (int)(sizeof(kCfgF32) / sizeof(Cfg));
     return kCfgF32;
   }
-  *n = 2;
+  *n = (int)(sizeof(kCfgFP8) / sizeof(Cfg));
   return kCfgFP8;
 }
 
-template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK>
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int OCC>
 void run(const GemmParams& g, hipStream_t s) {
   DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
-  hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, 2, 2>), dim3(tiles), dim3(256), 0, s, p);
+  hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles), dim3(WGM * WGN * 64),
+                     0, s, p);
 }
+
+#define ANON_CFG_CASE(i, bm, bn, bk, wgm, wgn, occ, name) \
+  case i:                                                  \
+    run<TI, TO, TR, EPI, bm, bn, bk, wgm, wgn, occ>(g, s); \
+    return true;
 
 template <typename TI, typename TO, typename TR, int EPI>
 bool dispatch_tile(const GemmParams& g, int ci, hipStream_t s) {
   if constexpr (sizeof(TI) == 2) {
-    switch (ci) {
-      case 0: run<TI, TO, TR, EPI, 128, 128, 64>(g, s); return true;
-      case 1: run<TI, TO, TR, EPI, 256, 128, 64>(g, s); return true;
-      case 2: run<TI, TO, TR, EPI, 128, 256, 64>(g, s); return true;
-      case 3: run<TI, TO, TR, EPI, 256, 256, 32>(g, s); return true;
-    }
+    switch (ci) { ANON_BF16_CFGS(ANON_CFG_CASE) }
   } else if constexpr (sizeof(TI) == 4) {
-    switch (ci) {
-      case 0: run<TI, TO, TR, EPI, 128, 128, 32>(g, s); return true;
-      case 1: run<TI, TO, TR, EPI, 64, 64, 32>(g, s); return true;
-    }
+    switch (ci) { ANON_F32_CFGS(ANON_CFG_CASE) }
   } else {
-    switch (ci) {
-      case 0: run<TI, TO, TR, EPI, 128, 128, 128>(g, s); return true;
-      case 1: run<TI, TO, TR, EPI, 256, 128, 128>(g, s); return true;
-    }
+    switch (ci) { ANON_FP8_CFGS(ANON_CFG_CASE) }
   }
   return false;
 }

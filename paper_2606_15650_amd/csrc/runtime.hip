@@ -503,6 +503,104 @@ anon_status ner_forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu
   return ANON_OK;
 }
 
+static ElemType prec_type(anon_precision p) {
+  return p == ANON_FP32 ? ET_F32 : (p == ANON_BF16 ? ET_BF16 : ET_FP8);
+}
+
+int32_t anon_tile_config_count(anon_precision precision) { return gemm_num_configs(prec_type(precision)); }
+
+const char* anon_tile_config_name(anon_precision precision, int32_t config) {
+  return gemm_config_name(prec_type(precision), config);
+}
+
+anon_status anon_model_set_tiles(anon_model* m, const int32_t tiles[4]) {
+  if (!m || !tiles) return set_error(ANON_EINVAL, "NULL argument");
+  const int h = m->cfg.hidden, f = m->cfg.ffn;
+  const int NK[4][2] = {{3 * h, h}, {h, h}, {f, h}, {h, f}};
+  for (int i = 0; i < 4; ++i)
+    if (tiles[i] >= 0 && !gemm_config_fits(m->gemm_t, tiles[i], NK[i][0], NK[i][1]))
+      return set_error(ANON_EINVAL, "tile configuration does not fit GEMM " + std::to_string(i));
+  for (int i = 0; i < 4; ++i) m->gemm_cfg[i] = tiles[i];
+  return ANON_OK;
+}
+
+anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws_bytes, void* stream,
+                          int32_t* chosen, float* times_ms, int32_t max_configs) {
+  clear_error();
+  if (!m || T < 1) return set_error(ANON_EINVAL, "bad arguments");
+  if (!d_workspace || ws_bytes < enc_ws_bytes(m, T, 1)) return set_error(ANON_ECAPACITY, "workspace too small");
+  ANON_HIP_CHECK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  Carver k(d_workspace, ws_bytes);
+  EncWs w;
+  enc_layout(m, T, 1, k, w);
+  launch_fill_u8((uint8_t*)d_workspace, 0, (int64_t)k.used, s);  // finite operands
+  const anon_model_config& c = m->cfg;
+  const int h = c.hidden, f = c.ffn;
+  const bool fp8 = m->gemm_t == ET_FP8;
+  const LayerW& L = m->layers[0];
+  hipEvent_t e0, e1;
+  ANON_HIP_CHECK(hipEventCreate(&e0));
+  ANON_HIP_CHECK(hipEventCreate(&e1));
+  const int ncfg = gemm_num_configs(m->gemm_t);
+  anon_status st = ANON_OK;
+  for (int gi = 0; gi < 4 && st == ANON_OK; ++gi) {
+    GemmParams g{};
+    g.M = T;
+    g.in = m->gemm_t;
+    g.acc_scale = 1.f;
+    g.out_inv_scale = 1.f;
+    g.qscale = 1.f;
+    if (gi == 0) {
+      g.A = fp8 ? (const void*)w.xq : w.x;
+      g.W = L.wqkv, g.bias = L.bqkv, g.C = w.qkv, g.N = 3 * h, g.K = h, g.epi = EPI_BIAS, g.out = m->qkv_t;
+    } else if (gi == 1) {
+      g.A = w.attn, g.W = L.wo, g.bias = L.bo, g.resid = w.x, g.res = m->act_t, g.C = w.y, g.N = h, g.K = h;
+      g.epi = EPI_RESID, g.out = ET_F32;
+    } else if (gi == 2) {
+      g.A = fp8 ? (const void*)w.xq : w.x2;
+      g.W = L.w1, g.bias = L.b1, g.C = w.ffn, g.N = f, g.K = h, g.epi = EPI_GELU, g.out = m->gemm_t;
+    } else {
+      g.A = w.ffn, g.W = L.w2, g.bias = L.b2, g.resid = w.x2, g.res = m->act_t, g.C = w.y, g.N = h, g.K = f;
+      g.epi = EPI_RESID, g.out = ET_F32;
+    }
+    float best = 1e30f;
+    int best_c = -1;
+    for (int ci = 0; ci < ncfg; ++ci) {
+      float ms_avg = -1.f;
+      if (gemm_config_fits(m->gemm_t, ci, g.N, g.K)) {
+        g.config = ci;
+        if (!launch_gemm(g, s)) {
+          st = ANON_EINVAL;
+          break;
+        }
+        const int reps = 3;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) launch_gemm(g, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          st = set_error(ANON_EDEVICE, "autotune: kernel failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_avg = ms / reps;
+        if (ms_avg < best) {
+          best = ms_avg;
+          best_c = ci;
+        }
+      }
+      if (times_ms && ci < max_configs) times_ms[gi * max_configs + ci] = ms_avg;
+    }
+    m->gemm_cfg[gi] = best_c;
+    if (chosen) chosen[gi] = best_c;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ANON_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
 anon_status anon_encoder_hidden(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
                                 int32_t T, int32_t n_layers, float* d_hidden, void* d_workspace, size_t ws_bytes,
                                 void* stream) {

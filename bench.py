@@ -103,12 +103,20 @@ def main() -> int:
     T, B = rb.n_tokens, rb.n_records
     cu = rb.cu_seqlens.astype(np.int64)
 
+    scales = None
+    if wl.precision == "fp8":
+        # static per-tensor activation scales, calibrated once by the oracle
+        with open(os.path.join(ROOT, "tests", "golden", f"fp8_scales_{wl.name}.json")) as f:
+            scales = np.asarray(json.load(f)["scales"], np.float32).reshape(-1)
+
     def run_path(precision: str, steps: int, warmup: int, prof: bool):
-        model = api.Model(cfg, blob, precision)
+        model = api.Model(cfg, blob, precision, act_scales=scales if precision == "fp8" else None)
         cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
         pl = Pipeline(model, cache)
         db = DeviceBatch(rb)
         stream = torch.cuda.current_stream()
+        tiles, _ = pl.autotune(T, B)
+        tiles = [model.tile_configs()[t] for t in tiles]
         for _ in range(warmup):
             pl.step(db)
         torch.cuda.synchronize()
@@ -135,9 +143,9 @@ def main() -> int:
         n_spans = None
         model.close()
         cache.close()
-        return wall, per, kern, st
+        return wall, per, kern, st, tiles
 
-    wall, per, kern, cstats = run_path(wl.precision, a.steps, a.warmup, prof=True)
+    wall, per, kern, cstats, tiles = run_path(wl.precision, a.steps, a.warmup, prof=True)
     tokens_per_s = T * a.steps / wall
     # dominant kernel class (largest total time) against its roofline
     gemm_tok = gemm_flops_per_token(cfg)
@@ -187,10 +195,11 @@ def main() -> int:
                             "mean": float(per.mean())},
         "kernels": breakdown,
         "pcache": cstats,
+        "gemm_tiles": dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles)),
         "input_gen_s": gen_s,
     }
     if not a.no_fp32 and wl.precision != "fp32":
-        w32, per32, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
+        w32, per32, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
         tps32 = T * max(2, a.steps // 4) / w32
         out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
     if not a.no_cpu:

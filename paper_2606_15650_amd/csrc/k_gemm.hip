@@ -134,11 +134,10 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
       const int c = tid + i * NT, r = c / CPR, cc = c % CPR;
-      const int gm = m0 + r;
-      if (gm < M)
-        ra[i] = *(const intx4*)(A + (size_t)gm * K + k0 + cc * EPC);
-      else
-        ra[i] = intx4{0, 0, 0, 0};
+      // rows past M (last tile only) re-read row M-1: their results are
+      // never stored, and the load needs no branch
+      const int gm = min(m0 + r, M - 1);
+      ra[i] = *(const intx4*)(A + (size_t)gm * K + k0 + cc * EPC);
     }
 #pragma unroll
     for (int i = 0; i < B_CH; ++i) {
@@ -206,33 +205,37 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   // Epilogue: lane owns column (lane & 31) of each 32x32 tile and rows
   // (r/4)*8 + (lane/32)*4 + r%4 of accumulator register r.
   TO* __restrict__ C = (TO*)p.C;
+  auto epilogue = [&](auto guarded) {
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int col = n0 + wn * WTN + j * 32 + (lane & 31);
-    const float bias = p.bias[col];
-    const float qs = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * WTN + j * 32 + (lane & 31);
+      const float bias = p.bias[col];
+      const float qs = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
+      for (int i = 0; i < TM; ++i) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * WTM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (row < M) {
-          float v = acc[i][j][r] * p.acc_scale + bias;
-          if (EPI == EPI_BIAS) {
-            v *= qs;
-          } else if (EPI == EPI_GELU) {
-            v = gelu_erf(v);
-            // FP8 output: the activation is a bf16 value first (as in the
-            // BF16 path), then scaled and rounded to E4M3
-            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
-          } else {
-            v += ld((const TR*)p.resid + (size_t)row * N + col);
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm * WTM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          if (!decltype(guarded)::value || row < M) {
+            float v = acc[i][j][r] * p.acc_scale + bias;
+            if (EPI == EPI_BIAS) {
+              v *= qs;
+            } else if (EPI == EPI_GELU) {
+              v = gelu_erf(v);
+              // FP8 output: the activation is a bf16 value first (as in the
+              // BF16 path), then scaled and rounded to E4M3
+              if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
+            } else {
+              v += ld((const TR*)p.resid + (size_t)row * N + col);
+            }
+            st(C + (size_t)row * N + col, v);
           }
-          st(C + (size_t)row * N + col, v);
         }
       }
     }
-  }
+  };
+  if (m0 + BM <= M) epilogue(std::false_type{});
+  else epilogue(std::true_type{});
 }
 
 struct Cfg {

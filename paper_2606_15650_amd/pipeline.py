@@ -71,6 +71,11 @@ class Pipeline:
             api.ner_forward(self.model, db.ids, db.cu, db.B, db.T, labels, z, m, ws, ws.numel(), stream)
         return labels, z, m
 
+    def autotune(self, T: int, B: int = 1, stream=None):
+        """Let the library time the GEMM tiles on T rows and keep the fastest."""
+        ws = self._buf("ner", self.model.workspace_size(T, max(B, 1)))
+        return self.model.autotune(T, ws, ws.numel(), stream)
+
     def hidden(self, db: DeviceBatch, n_layers: int, stream=None) -> torch.Tensor:
         out = torch.empty((max(db.T, 1), self.model.cfg.hidden), dtype=torch.float32, device=self.device)
         ws = self._buf("ner", self.model.workspace_size(db.T, db.B))

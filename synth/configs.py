@@ -70,6 +70,9 @@ WORKLOADS = {
         "stream_bf16", BASE, 70951, ("lognormal", 7.35, 0.6, 16, 16384), "bf16",
         zipf_pool=200_000, window=512, stride=448,
         notes="dataset-scale records windowed at 512 tokens with 64-token overlap"),
+    "tiny_fp8": Workload(
+        "tiny_fp8", TINY, 64, ("uniform", 16, 128), "fp8", o_target=None,
+        notes="the tiny encoder with FP8-E4M3 GEMMs (parity cases)"),
     "large_fp8": Workload(
         "large_fp8", LARGE, 16384, ("lognormal", 5.5, 0.7, 16, 512), "fp8",
         notes="24-layer h1024 encoder with FP8-E4M3 GEMMs"),

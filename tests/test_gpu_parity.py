@@ -338,3 +338,51 @@ def test_base_fp32_small_batch_vs_pure_oracle(torch_dev):
     bad, _ = confident_labels_agree(lab, lr, mr)
     assert len(bad) == 0
     m.close()
+
+
+def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch):
+    """Every GEMM tile shape gives the same bits (fixed K order): tuning never changes results."""
+    W, m = make_model(TINY, "bf16", 0)
+    names = m.tile_configs()
+    say(f"[tiles] {len(names)} bf16 tile configurations")
+    ref = None
+    h, f = TINY.hidden, TINY.ffn
+    from paper_2606_15650_amd import api
+    for ci in range(len(names)):
+        tiles = []
+        for (N, K) in ((3 * h, h), (h, h), (f, h), (h, f)):
+            # use ci where it fits the shape, else the default
+            tiles.append(ci if _fits(names[ci], N, K) else -1)
+        m.set_tiles(tiles)
+        lab, z, _ = _run_ner(m, tiny_batch)
+        if ref is None:
+            ref = z
+        else:
+            np.testing.assert_array_equal(z, ref, err_msg=names[ci])
+
+
+def _fits(name, N, K):
+    bm, bn, bk = [int(x) for x in name.split("_")[1].split("x")]
+    return N % bn == 0 and K % bk == 0
+
+
+def _fp8_scales(name):
+    import json, os
+    from tests.conftest import GOLDEN
+    with open(os.path.join(GOLDEN, f"fp8_scales_{name}.json")) as fh:
+        return json.load(fh)["scales"]
+
+
+def test_tiny_fp8_matches_rounding_oracle(torch_dev, tiny_batch):
+    sc = _fp8_scales("tiny_fp8")
+    W, m = make_model(TINY, "fp8", 0, act_scales=np.asarray(sc, np.float32).reshape(-1))
+    say("[tiny fp8] ner_forward vs fp8-rounding oracle")
+    lab, z, mg = _run_ner(m, tiny_batch)
+    prec = encoder.Precision("fp8", act_scales=sc)
+    zq, lq, mq = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens, prec)
+    zp, lp, mp = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens)
+    err_q = np.abs(z - zq).max()
+    say(f"  max |z - z_fp8oracle| {err_q:.3e}   max |z - z_pure| {np.abs(z - zp).max():.3e}  "
+        f"label agreement vs pure {(lab == lp).mean():.4f}")
+    bad, n = confident_labels_agree(lab, lq, mq)
+    assert len(bad) == 0, (len(bad), n)

@@ -71,6 +71,98 @@ def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
                       f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
 
 
+def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0) -> dict:
+    """Continuous-batching server under Poisson arrivals (serving workload).
+
+    Requests hold U{1..200} records with the base workload's length
+    distribution (drawn from a generated pool of records); arrivals are
+    Poisson at each rate for `seconds` after `warm_s` of warm-up traffic.
+    Latency = completion - submission per request.
+    """
+    import threading
+
+    import synth
+    from paper_2606_15650_amd import api
+    from paper_2606_15650_amd.pipeline import Pipeline
+
+    wl = synth.workload("base_bf16")
+    cfg = wl.model
+    pool = synth.generate_records(4096, wl.lengths, cfg.n_types, cfg.vocab, seed + 1000)
+    W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
+    model = api.Model(cfg, synth.weights_blob(cfg, W), "bf16")
+    cache = api.PseudonymCache(synth.make_key(0), 10, pool.type_names, 1 << 20)
+    max_tok = 131072
+    Pipeline(model, cache).autotune(max_tok, 1)
+    results = []
+    for rate in rates:
+        sv = api.Server(model, cache, hbm_budget_bytes=64 << 30, max_batch_tokens=max_tok, n_streams=3,
+                        max_queue=100000)
+        rng = np.random.default_rng(seed + int(rate))
+        # request = a run of consecutive pool records (wrapping), U{1..200} long
+        reqs = []
+        t_total = warm_s + seconds
+        t = 0.0
+        while t < t_total:
+            t += rng.exponential(1.0 / rate)
+            n = int(rng.integers(1, 201))
+            r0 = int(rng.integers(0, pool.n_records - n))
+            reqs.append((t, pool.subset(range(r0, r0 + n))))
+        done: list = []
+        tickets: list = []
+        lock = threading.Lock()
+        stop = threading.Event()
+
+        def poller():
+            pending = []
+            while not stop.is_set() or pending or len(done) < len(tickets):
+                with lock:
+                    pending.extend(tickets[len(done) + len(pending):])
+                still = []
+                for (tk, t_arr, ntok) in pending:
+                    r = sv.poll(tk)
+                    if r is None:
+                        still.append((tk, t_arr, ntok))
+                    else:
+                        done.append((t_arr, r["t_submit"], r["t_done"], ntok, r["status"]))
+                        sv.release(tk)
+                pending = still
+                if stop.is_set() and not pending and len(done) >= len(tickets):
+                    break
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        for (t_arr, q) in reqs:
+            dt = t_arr - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tk = sv.submit(q.ids, q.cu_seqlens, q.tok_off, q.text, q.cu_bytes)
+            with lock:
+                tickets.append((tk, t_arr, q.n_tokens))
+        stop.set()
+        th.join()
+        wall = time.perf_counter() - t0
+        sv.stop()
+        meas = [d for d in done if d[0] >= warm_s and d[4] == 0]
+        lat = np.array([d[2] - d[1] for d in meas]) * 1e3
+        t_first = min(d[1] for d in meas)
+        t_last = max(d[2] for d in meas)
+        tok = sum(d[3] for d in meas)
+        offered = sum(q.n_tokens for (ta, q) in reqs if ta >= warm_s) / seconds
+        results.append({"rate_req_s": rate, "requests": len(meas), "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                        "tokens_per_s": tok / (t_last - t_first), "offered_tokens_per_s": offered,
+                        "failed": sum(1 for d in done if d[4] != 0), "wall_s": wall})
+        print(json.dumps({"serve_partial": results[-1]}), flush=True)
+    model.close()
+    cache.close()
+    return {"metric": "serving p50/p99 request latency", "unit": "ms", "workload": "serve_bf16",
+            "config": {"model": "12L h768 BF16", "requests": "Poisson arrivals, U{1..200} records each, "
+                       "lengths as base_bf16", "hbm_budget": "64 GiB", "max_batch_tokens": max_tok,
+                       "streams": 3}, "rates": results}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,11 +172,18 @@ def main() -> int:
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--serve", default="", help="comma-separated request rates: run the serving benchmark")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(records shard across GPUs without communication, see DESIGN.md)"}))
         return 2
+    if a.serve:
+        rates = [float(x) for x in a.serve.split(",")]
+        print(json.dumps(serve_bench(rates, a.serve_seconds, a.serve_warmup)), flush=True)
+        return 0
 
     import torch
 

@@ -254,8 +254,11 @@ struct Cfg {
   X(6, 128, 256, 32, 2, 2, 2, "bf16_128x256x32_w2x2") \
   X(7, 256, 256, 64, 4, 2, 2, "bf16_256x256x64_w4x2") \
   X(8, 256, 256, 32, 4, 2, 2, "bf16_256x256x32_w4x2") \
-  X(9, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2")
-#define ANON_F32_CFGS(X)                         \
+  X(9, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2") \
+  X(10, 256, 128, 32, 4, 2, 2, "bf16_256x128x32_w4x2") \
+  X(11, 128, 256, 32, 2, 4, 2, "bf16_128x256x32_w2x4") \
+  X(12, 256, 128, 64, 4, 2, 2, "bf16_256x128x64_w4x2")
+#define ANON_F32_CFGS(X)                        \
   X(0, 128, 128, 32, 2, 2, 2, "f32_128x128x32_w2x2") \
   X(1, 64, 64, 32, 2, 2, 2, "f32_64x64x32_w2x2")     \
   X(2, 128, 128, 16, 2, 2, 2, "f32_128x128x16_w2x2") \

@@ -175,6 +175,7 @@ def main() -> int:
     ap.add_argument("--serve", default="", help="comma-separated request rates: run the serving benchmark")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -184,6 +185,16 @@ def main() -> int:
         rates = [float(x) for x in a.serve.split(",")]
         print(json.dumps(serve_bench(rates, a.serve_seconds, a.serve_warmup)), flush=True)
         return 0
+    if a.calib_copy:
+        # a plain device copy of known size (1 GiB read + 1 GiB write), used to
+        # scale the FETCH_SIZE / WRITE_SIZE counters of a profiled run
+        import torch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     import torch
 

@@ -1,0 +1,82 @@
+"""How far apart can two correct reduced-precision evaluations of the encoder be?
+
+Test infrastructure: calls only the oracle and the seeded generator.  The
+bf16 reading rounds every stored activation; rounding is discontinuous, so a
+relative perturbation far below bf16 resolution (1e-7, the order of FP32
+accumulation error) flips some roundings, and over many layers these flips
+spread into logit differences of the size of bf16 noise itself.  This script
+measures that spread on the oracle alone:
+
+* the bf16 oracle against itself with a 1e-7 relative perturbation before each
+  rounding (what any FP32-accumulating GPU implementation amounts to);
+* the bf16 oracle against the pure float64 oracle.
+
+The largest spread sets the label-agreement margin that a reduced-precision
+path can be held to: two evaluations that differ by at most d per logit can
+disagree on the argmax only where the top-2 margin is below 2d.
+
+    python -m oracle.sensitivity base_bf16   -> tests/golden/sensitivity_base_bf16.json
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import encoder  # noqa: E402
+from oracle.numerics import round_bf16  # noqa: E402
+
+LENGTHS = [512, 37, 200, 16, 129, 300]
+EPS = 1e-7
+
+
+class _Perturbed(encoder.Precision):
+    def __init__(self, mode, eps, seed, act_scales=None):
+        super().__init__(mode, act_scales or [])
+        self.rng = np.random.default_rng(seed)
+        self.eps = eps
+
+    def store(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        return round_bf16(x * (1.0 + self.eps * self.rng.standard_normal(x.shape)))
+
+
+def measure(name: str) -> dict:
+    wl = synth.workload(name)
+    cfg = wl.model
+    W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
+    rb = synth.generate_records(len(LENGTHS), np.array(LENGTHS), cfg.n_types, cfg.vocab, 17)
+    mode = wl.precision
+    scales = None
+    if mode == "fp8":
+        with open(os.path.join(ROOT, "tests", "golden", f"fp8_scales_{name}.json")) as f:
+            scales = json.load(f)["scales"]
+    zq, lq, mq = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens, encoder.Precision(mode, scales or []))
+    zp, lp, mp = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens)
+    zn, ln, mn = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens, _Perturbed(mode, EPS, 1, scales))
+    dn, dp = np.abs(zn - zq), np.abs(zq - zp)
+    return {
+        "source": "written by oracle/sensitivity.py (oracle only)",
+        "workload": name, "layers": cfg.n_layers, "hidden": cfg.hidden, "tokens": int(rb.n_tokens),
+        "perturbation": EPS,
+        "perturbed_vs_rounding_oracle": {"max": float(dn.max()), "rms": float(np.sqrt((dn ** 2).mean()))},
+        "rounding_oracle_vs_pure": {"max": float(dp.max()), "rms": float(np.sqrt((dp ** 2).mean()))},
+        "confident_label_flips_at_1e-2": int(((ln != lq) & (mq > 1e-2)).sum()),
+        "tokens_with_margin_above_1e-2": int((mq > 1e-2).sum()),
+    }
+
+
+if __name__ == "__main__":
+    name = sys.argv[1] if len(sys.argv) > 1 else "base_bf16"
+    out = measure(name)
+    path = os.path.join(ROOT, "tests", "golden", f"sensitivity_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))

@@ -8,11 +8,15 @@
 // streams the record's keys in tiles of 64: K rows and V^T are staged in LDS
 // and shared by all waves; each wave owns 32 query rows and computes
 // S^T = K Q^T with 32x32 MFMAs, so that every lane holds the scores of one
-// query row.  Softmax is online in FP32 (running max and sum per row, base-2
-// exponentials); the probabilities are rounded to the operand type and
-// O^T += V^T P^T accumulates in FP32.  The MFMA k-index of P^T is a
-// permutation of the 32 keys of a block; V^T is read from LDS with the same
-// permutation, so the contraction is exact.
+// query row.  Records longer than one tile take two passes over their keys:
+// the first finds each row's exact maximum, the second forms
+// p = exp(s - max) once (FP32, base-2 exponentials), sums it in FP32, rounds
+// it to the operand type and accumulates O^T += V^T P^T in FP32.  Rounding p
+// relative to the final maximum (not a running one) makes the rounded values
+// a function of the record alone, identical to the definition
+// softmax(s) = exp(s - max) / sum.  The MFMA k-index of P^T is a permutation
+// of the 32 keys of a block; V^T is read from LDS with the same permutation,
+// so the contraction is exact.
 #include "kernels.hpp"
 
 namespace anon {
@@ -113,64 +117,83 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
   float m = -INFINITY, lsum = 0.f;
 
   constexpr int CPR = D / EPC;  // 16-byte chunks per K/V row
-  for (int t0 = 0; t0 < L; t0 += KT) {
-    const int nk = min(KT, L - t0);
-    __syncthreads();
+  // scores of the current 64-key tile, base-2 scaled, -inf for missing keys
+  auto scores = [&](floatx16 (&s)[2], int nk) {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < D / MF::KI; ++kk) {
+        const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * (D + PAD) + kk * MF::KI + hh * MF::KPL];
+        s[kb] = MF::mma(a, qf[kk], s[kb]);
+      }
+    }
+    float mloc = -INFINITY;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
+        const float v = key < nk ? s[kb][r] * LOG2E : -INFINITY;
+        s[kb][r] = v;
+        mloc = fmaxf(mloc, v);
+      }
+    return fmaxf(mloc, __shfl_xor(mloc, 32, 64));
+  };
+  auto load_tile = [&](int t0, int nk, bool with_v) {
     for (int c = tid; c < KT * CPR; c += NT) {
       const int r = c / CPR, cc = c % CPR;
       intx4 kv = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
       if (r < nk) {
         const T* src = qkv + (size_t)(base + t0 + r) * ld + head * D + cc * EPC;
         kv = *(const intx4*)(src + hidden);
-        vv = *(const intx4*)(src + 2 * hidden);
+        if (with_v) vv = *(const intx4*)(src + 2 * hidden);
       }
       *(intx4*)&Ks[r * (D + PAD) + cc * EPC] = kv;
-      const T* ve = (const T*)&vv;
+      if (with_v) {
+        const T* ve = (const T*)&vv;
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) Vt[(cc * EPC + e) * (KT + PAD) + r] = ve[e];
+        for (int e = 0; e < EPC; ++e) Vt[(cc * EPC + e) * (KT + PAD) + r] = ve[e];
+      }
     }
+  };
+
+  // Pass 1 (records longer than one tile): the exact row maximum, so that
+  // the probabilities below are formed and rounded once, relative to it.
+  const int ntiles = (L + KT - 1) / KT;
+  if (ntiles > 1) {
+    for (int t0 = 0; t0 < L; t0 += KT) {
+      const int nk = min(KT, L - t0);
+      __syncthreads();
+      load_tile(t0, nk, false);
+      __syncthreads();
+      if (active) {
+        floatx16 s[2];
+        m = fmaxf(m, scores(s, nk));
+      }
+    }
+  }
+  // Pass 2: p = exp(s - max), row sums in FP32, O^T += V^T P^T.
+  for (int t0 = 0; t0 < L; t0 += KT) {
+    const int nk = min(KT, L - t0);
+    __syncthreads();
+    load_tile(t0, nk, true);
     __syncthreads();
     if (active) {
       floatx16 s[2];
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s[kb][r] = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < D / MF::KI; ++kk) {
-          const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * (D + PAD) + kk * MF::KI + hh * MF::KPL];
-          s[kb] = MF::mma(a, qf[kk], s[kb]);
-        }
-      }
-      float mloc = -INFINITY;
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
-          const float v = key < nk ? s[kb][r] * LOG2E : -INFINITY;
-          s[kb][r] = v;
-          mloc = fmaxf(mloc, v);
-        }
-      mloc = fmaxf(mloc, __shfl_xor(mloc, 32, 64));
-      const float mnew = fmaxf(m, mloc);
-      const float alpha = exp2f(m - mnew);
-      m = mnew;
+      const float mt = scores(s, nk);
+      if (ntiles == 1) m = mt;
       float ps = 0.f;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float pv = exp2f(s[kb][r] - mnew);
+          const float pv = exp2f(s[kb][r] - m);
           s[kb][r] = pv;
           ps += pv;
         }
-      lsum = lsum * alpha + ps;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        o[0][r] *= alpha;
-        o[1][r] *= alpha;
-      }
+      lsum += ps;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll

@@ -11,6 +11,15 @@ from synth.configs import ModelConfig
 MARGIN = 1e-2        # labels must agree where the reference margin exceeds this
 FP32_LOGIT_RTOL = 1e-4
 
+# Reduced precision: (max logit deviation from the rounding oracle, label margin).
+# Two evaluations within d per logit can only disagree where the top-2 margin
+# is below 2d.  At 2 layers the deviation stays near 1e-3, so the 1e-2 margin
+# holds.  At 12 layers the oracle itself, perturbed by 1e-7 before each bf16
+# rounding, moves by up to 0.017 (tests/golden/sensitivity_base_bf16.json):
+# no bf16 implementation can be held closer, so the bound is 0.03 and the
+# label margin 0.06; agreement above 1e-2 is still measured and reported.
+REDUCED_GATE = {("bf16", 2): (5e-3, 1e-2), ("fp8", 2): (5e-3, 1e-2), ("bf16", 12): (3e-2, 6e-2)}
+
 
 def say(*a):
     print(*a, flush=True)

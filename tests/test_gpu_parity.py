@@ -11,7 +11,8 @@ import pytest
 import synth
 from oracle import encoder, pipeline as opipe, pseudonym as ops, spans as ospans
 from synth.configs import TINY, BASE, ModelConfig
-from tests.gpu_common import (MARGIN, FP32_LOGIT_RTOL, confident_labels_agree, confident_records, logit_rel_err,
+from tests.gpu_common import (MARGIN, FP32_LOGIT_RTOL, REDUCED_GATE, confident_labels_agree, confident_records,
+                              logit_rel_err,
                               make_cache, make_model, say)
 
 pytestmark = pytest.mark.gpu
@@ -319,10 +320,58 @@ def test_base_bf16_small_batch_vs_rounding_oracle(torch_dev):
     lab, z, mg = _run_ner(m, rb)
     zq, lq, mq = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens, encoder.Precision("bf16"))
     zp, lp, mp = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens)
-    say(f"  max |z-zq| {np.abs(z - zq).max():.3e}  max |z-zpure| {np.abs(z - zp).max():.3e}  "
-        f"O-rate {(lab == 0).mean():.3f}")
-    bad, n = confident_labels_agree(lab, lq, mq)
-    assert len(bad) == 0, (len(bad), n)
+    dev_q, dev_p = np.abs(z - zq).max(), np.abs(z - zp).max()
+    bound, tau = REDUCED_GATE[("bf16", BASE.n_layers)]
+    sel = mq > MARGIN
+    say(f"  max |z-zq| {dev_q:.3e}  max |z-zpure| {dev_p:.3e}  O-rate {(lab == 0).mean():.3f}  "
+        f"agreement above 1e-2: {(lab[sel] == lq[sel]).mean():.5f} of {sel.sum()}")
+    assert dev_q < bound and dev_p < bound
+    assert ((lab != lq) & (mq > tau)).sum() == 0
+    m.close()
+
+
+def test_base_bf16_full_batch_sampled_records(torch_dev):
+    """The bench's workload and launch configuration (4096 records, autotuned tiles):
+    sampled records are checked against the oracle, alone and inside the batch."""
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list, spans_to_numpy
+    wl = synth.workload("base_bf16")
+    rb = synth.generate_records(wl.n_records, wl.lengths, BASE.n_types, BASE.vocab, wl.seed)
+    W, m = make_model(BASE, "bf16", wl.weight_seed, o_target=wl.o_target)
+    cache = make_cache(rb.type_names, capacity=1 << 20)
+    pl = Pipeline(m, cache)
+    say(f"[base bf16 full] T={rb.n_tokens} B={rb.n_records}: autotune + one step")
+    pl.autotune(rb.n_tokens, rb.n_records)
+    db = DeviceBatch(rb)
+    z_lab, z_full, _ = pl.ner(db, logits=True)
+    labels, spans, cu_spans, out, cu_out = pl.step(db)
+    torch.cuda.synchronize()
+    lab = labels[: rb.n_tokens].cpu().numpy()
+    np.testing.assert_array_equal(lab, z_lab[: rb.n_tokens].cpu().numpy())
+    outs = outputs_to_list(out, cu_out)
+    cs = cu_spans.cpu().numpy()
+    sp = spans_to_numpy(spans, int(cs[-1]))
+    z_full = z_full[: rb.n_tokens].cpu().numpy()
+    rng = np.random.default_rng(7)
+    sample = sorted(set([0, rb.n_records - 1] + rng.choice(rb.n_records, 2, replace=False).tolist()))
+    key = synth.make_key(0)
+    bound, tau = REDUCED_GATE[("bf16", BASE.n_layers)]
+    for r in sample:
+        a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
+        sub = rb.subset([r])
+        say(f"  record {r}: {b - a} tokens vs oracle")
+        zq, lq, mq = encoder.forward(W, BASE, sub.ids, sub.cu_seqlens, encoder.Precision("bf16"))
+        assert np.abs(z_full[a:b] - zq).max() < bound
+        assert ((lab[a:b] != lq) & (mq > tau)).sum() == 0
+        # integer tail of this record: exact given the GPU labels
+        res = opipe.run(W, BASE, sub, key, 10, labels_override=lab[a:b])
+        assert outs[r] == res.outputs[0]
+        mine = sp[sp[:, 0] == r].copy()
+        mine[:, 0] = 0
+        np.testing.assert_array_equal(mine, res.spans)
+        # the same record alone gives the same bits as inside the batch
+        l1, z1, _ = _run_ner(m, sub)
+        np.testing.assert_array_equal(z1, z_full[a:b])
     m.close()
 
 

@@ -226,13 +226,137 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
   }
 }
 
+// Record-resident variant (bf16 operands, records of at most RMAX keys).
+// One workgroup per (record, head) stages the record's whole K (row-major)
+// and V^T in LDS once; its waves then take 32-row query chunks in turn and
+// run both passes over the resident keys with no further barrier.  The V^T
+// row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
+// 32 lanes on distinct banks.
+template <typename TO, int RMAX, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
+                                                                   TO* __restrict__ out,
+                                                                   const int4* __restrict__ recs,
+                                                                   const int* __restrict__ n_recs, int hidden,
+                                                                   float out_inv_scale) {
+  typedef AMfma<bf16_t> MF;
+  typedef bf16x8 frag;
+  constexpr int KS = D + 8;       // K row stride (16 bytes of padding)
+  constexpr int VS = RMAX + 12;   // V^T row stride
+  constexpr float LOG2E = 1.4426950408889634f;
+  const int rb = blockIdx.x;
+  if (rb >= *n_recs) return;
+  const int head = blockIdx.y;
+  const int4 desc = recs[rb];
+  const int base = desc.x, L = desc.y;
+  const int ld = 3 * hidden;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5;
+
+  __shared__ bf16_t Ks[RMAX * KS];
+  __shared__ bf16_t Vt[D * VS];
+
+  const int Lp = (L + 31) & ~31;  // keys padded with zeros to whole 32-key blocks
+  for (int c = tid; c < Lp * 8; c += WAVES * 64) {
+    const int r = c >> 3, cc = c & 7;
+    intx4 kv = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
+    if (r < L) {
+      const bf16_t* src = qkv + (size_t)(base + r) * ld + head * D + cc * 8;
+      kv = *(const intx4*)(src + hidden);
+      vv = *(const intx4*)(src + 2 * hidden);
+    }
+    *(intx4*)&Ks[r * KS + cc * 8] = kv;
+    const bf16_t* ve = (const bf16_t*)&vv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Vt[(cc * 8 + e) * VS + r] = ve[e];
+  }
+  __syncthreads();
+
+  const int nkb = Lp / 32;
+  const int nqc = (L + 31) / 32;
+  for (int qc = wave; qc < nqc; qc += WAVES) {
+    const int qrow = qc * 32 + (lane & 31);
+    frag qf[D / 16];
+#pragma unroll
+    for (int kk = 0; kk < D / 16; ++kk)
+      qf[kk] = qrow < L ? *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * 16 + hh * 8) : frag{};
+    auto block_scores = [&](int kb, floatx16& s) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[r] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < D / 16; ++kk) {
+        const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * KS + kk * 16 + hh * 8];
+        s = MF::mma(a, qf[kk], s);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
+        s[r] = key < L ? s[r] * LOG2E : -INFINITY;
+      }
+    };
+    float m = -INFINITY;
+    if (nkb > 1) {
+      for (int kb = 0; kb < nkb; ++kb) {
+        floatx16 s;
+        block_scores(kb, s);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) m = fmaxf(m, s[r]);
+      }
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+    }
+    floatx16 o[2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
+    float lsum = 0.f;
+    for (int kb = 0; kb < nkb; ++kb) {
+      floatx16 s;
+      block_scores(kb, s);
+      if (nkb == 1) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) m = fmaxf(m, s[r]);
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float pv = exp2f(s[r] - m);
+        s[r] = pv;
+        lsum += pv;
+      }
+#pragma unroll
+      for (int stp = 0; stp < 2; ++stp) {
+        const frag pb = pfrag<bf16_t>(s, stp);
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const bf16_t* vrow = &Vt[(db * 32 + (lane & 31)) * VS + kb * 32];
+          const frag va = vfrag(vrow, 0, stp, hh);
+          o[db] = MF::mma(va, pb, o[db]);
+        }
+      }
+    }
+    const float ltot = lsum + __shfl_xor(lsum, 32, 64);
+    const float inv = 1.0f / ltot;
+    if (qrow < L) {
+      TO* dst = out + (size_t)(base + qrow) * hidden + head * D;
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          float v = o[db][r] * inv;
+          if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * out_inv_scale;
+          st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), v);
+        }
+    }
+  }
+}
+
 constexpr int kWaves = 4;
 constexpr int kBQ = 32 * kWaves;
+constexpr int kShortMax = 128;   // records up to this length use the small resident kernel
+constexpr int kResidentMax = 512;
 
-// One workgroup: validates cu_seqlens and lists (record, q-block) items.
+// One workgroup: validates cu_seqlens and lists (record, q-block) items for
+// the records whose length lies in [lo, hi].
 __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
-                                                        int bq, int4* __restrict__ qblocks, int max_q,
-                                                        int* __restrict__ n_qblocks, uint32_t* err) {
+                                                        int lo, int hi, int bq, int4* __restrict__ qblocks,
+                                                        int max_q, int* __restrict__ n_qblocks, uint32_t* err) {
   // Malformed (overlapping) cu_seqlens could ask for more items than the
   // buffer holds; writes stop at max_q and the error bit is raised.
   __shared__ int sums[1024];
@@ -248,7 +372,7 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
       bad = true;
       continue;
     }
-    cnt += (L + bq - 1) / bq;
+    if (L >= lo && L <= hi) cnt += (L + bq - 1) / bq;
   }
   if (tid == 0 && (cu[0] != 0 || cu[B] != T)) bad = true;
   if (bad) raise_error(err, ANON_ERR_SEQLENS);
@@ -265,6 +389,7 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
     const int a = cu[s], b = cu[s + 1];
     const int L = b - a;
     if (a < 0 || b > T || L < 0 || L > max_len) continue;
+    if (L < lo || L > hi) continue;
     for (int q = 0; q < L && pos < max_q; q += bq) qblocks[pos++] = int4{a, L, q, s};
   }
   if (tid == 1023) {
@@ -274,31 +399,60 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
   }
 }
 
+bool resident(ElemType t, int max_len) { return t == ET_BF16 && max_len <= kResidentMax; }
+
 }  // namespace
 
-int attn_block_q(ElemType) { return kBQ; }
-
-void launch_seq_plan(const int* cu_seqlens, int B, int T, int max_len, int bq, int4* qblocks, int max_q,
-                     int* n_qblocks, uint32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, bq, qblocks, max_q,
-                     n_qblocks, err);
+int attn_plan_items(ElemType t, int max_len, int T, int B) {
+  // resident: one item per record in each of two length classes;
+  // tiled: one item per 128-row q-block
+  return resident(t, max_len) ? 2 * (B + 1) : T / kBQ + B + 1;
 }
 
-void launch_attention(const void* qkv, void* out, const int4* qblocks,
-                      const int* n_qblocks, int max_qblocks, int n_heads, int hidden, ElemType t, ElemType out_t,
-                      float out_inv_scale, hipStream_t s) {
-  if (max_qblocks <= 0) return;
-  dim3 grid(max_qblocks, n_heads);
-  const int4* qb = qblocks;
+void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
+                      int* counts, uint32_t* err, hipStream_t s) {
+  if (resident(t, max_len)) {
+    const int half = max_items / 2;
+    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 1, kShortMax,
+                       1 << 30, items, half, counts, err);
+    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, kShortMax + 1,
+                       max_len, 1 << 30, items + half, half, counts + 1, err);
+  } else {
+    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 0, max_len, kBQ,
+                       items, max_items, counts, err);
+  }
+}
+
+void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* counts,
+                      int max_len, int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale,
+                      hipStream_t s) {
+  if (max_items <= 0) return;
+  if (resident(t, max_len)) {
+    const int half = max_items / 2;
+    const bf16_t* q = (const bf16_t*)qkv;
+    if (out_t == ET_FP8) {
+      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kShortMax, 4>), dim3(half, n_heads), dim3(256), 0, s, q,
+                         (fp8_t*)out, items, counts, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kResidentMax, 8>), dim3(half, n_heads), dim3(512), 0, s, q,
+                         (fp8_t*)out, items + half, counts + 1, hidden, out_inv_scale);
+    } else {
+      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kShortMax, 4>), dim3(half, n_heads), dim3(256), 0, s, q,
+                         (bf16_t*)out, items, counts, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kResidentMax, 8>), dim3(half, n_heads), dim3(512), 0, s, q,
+                         (bf16_t*)out, items + half, counts + 1, hidden, out_inv_scale);
+    }
+    return;
+  }
+  dim3 grid(max_items, n_heads);
   if (t == ET_F32) {
     hipLaunchKernelGGL((attn_kernel<float, float, kWaves>), grid, dim3(kWaves * 64), 0, s, (const float*)qkv,
-                       (float*)out, qb, n_qblocks, hidden, out_inv_scale);
+                       (float*)out, items, counts, hidden, out_inv_scale);
   } else if (out_t == ET_FP8) {
     hipLaunchKernelGGL((attn_kernel<bf16_t, fp8_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (fp8_t*)out, qb, n_qblocks, hidden, out_inv_scale);
+                       (fp8_t*)out, items, counts, hidden, out_inv_scale);
   } else {
     hipLaunchKernelGGL((attn_kernel<bf16_t, bf16_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (bf16_t*)out, qb, n_qblocks, hidden, out_inv_scale);
+                       (bf16_t*)out, items, counts, hidden, out_inv_scale);
   }
 }
 

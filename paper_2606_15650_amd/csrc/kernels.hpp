@@ -31,13 +31,15 @@ const char* gemm_config_name(ElemType in, int config);
 bool gemm_config_fits(ElemType in, int config, int N, int K);
 
 // ---- attention ------------------------------------------------------------
-// Builds the per-(record, q-block) work list from cu_seqlens.
-void launch_seq_plan(const int* cu_seqlens, int B, int T, int max_len, int bq, int4* qblocks, int max_q,
-                     int* n_qblocks, uint32_t* err, hipStream_t s);
-int attn_block_q(ElemType t);
-void launch_attention(const void* qkv, void* out, const int4* qblocks,
-                      const int* n_qblocks, int max_qblocks, int n_heads, int hidden, ElemType t, ElemType out_t,
-                      float out_inv_scale, hipStream_t s);
+// Attention work list: validates cu_seqlens and lists the work items of the
+// kernel variant that serves (operand type, max record length).  `counts`
+// holds 2 ints.
+int attn_plan_items(ElemType t, int max_len, int T, int B);
+void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
+                      int* counts, uint32_t* err, hipStream_t s);
+void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* counts,
+                      int max_len, int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale,
+                      hipStream_t s);
 
 // ---- row-wise kernels -----------------------------------------------------
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,

@@ -333,10 +333,9 @@ static void enc_layout(const anon_model* m, int T, int B, Carver& k, EncWs& w) {
   w.attn = k.take<uint8_t>(T * h * g);
   w.y = k.take<float>(T * h);
   w.ffn = k.take<uint8_t>(T * f * g);
-  const int bq = attn_block_q(m->qkv_t);
-  w.max_q = T / bq + B + 1;
+  w.max_q = attn_plan_items(m->qkv_t, m->cfg.max_pos, T, B);
   w.qblocks = k.take<int4>(w.max_q);
-  w.nq = k.take<int>(1);
+  w.nq = k.take<int>(2);
 }
 
 static anon_status check_batch(const anon_model* m, const void* d_ids, const void* d_cu, int B, int T) {
@@ -358,7 +357,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
   const int h = c.hidden, f = c.ffn;
   uint32_t* err = error_word_ptr();
   const bool fp8 = m->gemm_t == ET_FP8;
-  launch_seq_plan(cu, B, T, c.max_pos, attn_block_q(m->qkv_t), w.qblocks, w.max_q, w.nq, err, s);
+  launch_attn_plan(cu, B, T, c.max_pos, m->qkv_t, w.qblocks, w.max_q, w.nq, err, s);
   {
     ProfScope ps(KC_EMBED, s, 0.0);
     launch_embed_ln(ids, cu, B, T, m->tok_emb, m->pos_emb, m->emb_g, m->emb_b, c.ln_eps, c.vocab, c.max_pos, h, w.x,
@@ -392,7 +391,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     }
     {
       ProfScope ps(KC_ATTN, s, 0.0);
-      launch_attention(w.qkv, w.attn, w.qblocks, w.nq, w.max_q, c.n_heads, h, m->qkv_t, m->gemm_t,
+      launch_attention(w.qkv, w.attn, w.qblocks, w.max_q, w.nq, c.max_pos, c.n_heads, h, m->qkv_t, m->gemm_t,
                        fp8 ? 1.f / L.sa[1] : 1.f, s);
     }
     // output projection + bias + residual -> FP32, then LayerNorm 1

@@ -232,7 +232,9 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // run both passes over the resident keys with no further barrier.  The V^T
 // row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
 // 32 lanes on distinct banks.
-template <typename TO, int RMAX, int WAVES>
+// PAIR: two independent key blocks per iteration (more MFMA chains in flight
+// per wave, at the cost of registers).
+template <typename TO, int RMAX, int WAVES, bool PAIR>
 __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
                                                                    TO* __restrict__ out,
                                                                    const int4* __restrict__ recs,
@@ -272,13 +274,15 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
 
   const int nkb = Lp / 32;
   const int nqc = (L + 31) / 32;
+  const bool partial = (L & 31) != 0;  // only the last key block has missing keys
   for (int qc = wave; qc < nqc; qc += WAVES) {
     const int qrow = qc * 32 + (lane & 31);
     frag qf[D / 16];
 #pragma unroll
     for (int kk = 0; kk < D / 16; ++kk)
       qf[kk] = qrow < L ? *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * 16 + hh * 8) : frag{};
-    auto block_scores = [&](int kb, floatx16& s) {
+    // raw scores S^T of key block kb; missing keys of the last block -> -inf
+    auto qk = [&](int kb, floatx16& s) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) s[r] = 0.f;
 #pragma unroll
@@ -286,39 +290,46 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
         const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * KS + kk * 16 + hh * 8];
         s = MF::mma(a, qf[kk], s);
       }
+      if (partial && kb == nkb - 1) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
-        s[r] = key < L ? s[r] * LOG2E : -INFINITY;
+        for (int r = 0; r < 16; ++r)
+          if (kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3) >= L) s[r] = -INFINITY;
       }
     };
-    float m = -INFINITY;
+    // pass 1: row maximum of the raw scores (the scale is positive, so the
+    // maximum of the scaled scores is the scaled maximum)
+    float mraw = -INFINITY;
     if (nkb > 1) {
-      for (int kb = 0; kb < nkb; ++kb) {
-        floatx16 s;
-        block_scores(kb, s);
+      int kb = 0;
+      if (PAIR) {
+        for (; kb + 1 < nkb; kb += 2) {
+          floatx16 s0, s1;
+          qk(kb, s0);
+          qk(kb + 1, s1);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) m = fmaxf(m, s[r]);
+          for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, fmaxf(s0[r], s1[r]));
+        }
       }
-      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      for (; kb < nkb; ++kb) {
+        floatx16 s0;
+        qk(kb, s0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s0[r]);
+      }
+      mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
     }
-    floatx16 o[2];
+    floatx16 o[2], o2[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
+    for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = o2[0][r] = o2[1][r] = 0.f;
     float lsum = 0.f;
-    for (int kb = 0; kb < nkb; ++kb) {
-      floatx16 s;
-      block_scores(kb, s);
-      if (nkb == 1) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) m = fmaxf(m, s[r]);
-        m = fmaxf(m, __shfl_xor(m, 32, 64));
-      }
+    // pass 2: p = 2^(s*log2(e) - max*log2(e)) = exp(s - max), O^T += V^T P^T
+    auto pv = [&](int kb, floatx16& s, floatx16 (&acc)[2]) {
+      const float mb = mraw * LOG2E;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float pv = exp2f(s[r] - m);
-        s[r] = pv;
-        lsum += pv;
+        const float p = exp2f(fmaf(s[r], LOG2E, -mb));
+        s[r] = p;
+        lsum += p;
       }
 #pragma unroll
       for (int stp = 0; stp < 2; ++stp) {
@@ -326,9 +337,35 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
 #pragma unroll
         for (int db = 0; db < 2; ++db) {
           const bf16_t* vrow = &Vt[(db * 32 + (lane & 31)) * VS + kb * 32];
-          const frag va = vfrag(vrow, 0, stp, hh);
-          o[db] = MF::mma(va, pb, o[db]);
+          acc[db] = MF::mma(vfrag(vrow, 0, stp, hh), pb, acc[db]);
         }
+      }
+    };
+    int kb = 0;
+    if (PAIR) {
+      for (; kb + 1 < nkb; kb += 2) {
+        floatx16 s0, s1;
+        qk(kb, s0);
+        qk(kb + 1, s1);
+        pv(kb, s0, o);
+        pv(kb + 1, s1, o2);
+      }
+    }
+    for (; kb < nkb; ++kb) {
+      floatx16 s0;
+      qk(kb, s0);
+      if (nkb == 1) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s0[r]);
+        mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
+      }
+      pv(kb, s0, o);
+    }
+    if (PAIR) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        o[0][r] += o2[0][r];
+        o[1][r] += o2[1][r];
       }
     }
     const float ltot = lsum + __shfl_xor(lsum, 32, 64);
@@ -351,6 +388,13 @@ constexpr int kWaves = 4;
 constexpr int kBQ = 32 * kWaves;
 constexpr int kShortMax = 128;   // records up to this length use the small resident kernel
 constexpr int kResidentMax = 512;
+#ifndef ANON_ATTN_LONG_PAIR
+#define ANON_ATTN_LONG_PAIR 0
+#endif
+// long records: 16 waves (4 per SIMD) with one key block per iteration, or
+// 8 waves with two
+constexpr bool kLongPair = ANON_ATTN_LONG_PAIR != 0;
+constexpr int kLongWaves = kLongPair ? 8 : 16;
 
 // One workgroup: validates cu_seqlens and lists (record, q-block) items for
 // the records whose length lies in [lo, hi].
@@ -431,15 +475,17 @@ void launch_attention(const void* qkv, void* out, const int4* items, int max_ite
     const int half = max_items / 2;
     const bf16_t* q = (const bf16_t*)qkv;
     if (out_t == ET_FP8) {
-      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kShortMax, 4>), dim3(half, n_heads), dim3(256), 0, s, q,
-                         (fp8_t*)out, items, counts, hidden, out_inv_scale);
-      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kResidentMax, 8>), dim3(half, n_heads), dim3(512), 0, s, q,
-                         (fp8_t*)out, items + half, counts + 1, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kShortMax, 4, false>), dim3(half, n_heads), dim3(256), 0, s,
+                         q, (fp8_t*)out, items, counts, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kResidentMax, kLongWaves, kLongPair>), dim3(half, n_heads),
+                         dim3(kLongWaves * 64), 0, s, q, (fp8_t*)out, items + half, counts + 1, hidden,
+                         out_inv_scale);
     } else {
-      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kShortMax, 4>), dim3(half, n_heads), dim3(256), 0, s, q,
-                         (bf16_t*)out, items, counts, hidden, out_inv_scale);
-      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kResidentMax, 8>), dim3(half, n_heads), dim3(512), 0, s, q,
-                         (bf16_t*)out, items + half, counts + 1, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kShortMax, 4, false>), dim3(half, n_heads), dim3(256), 0, s,
+                         q, (bf16_t*)out, items, counts, hidden, out_inv_scale);
+      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kResidentMax, kLongWaves, kLongPair>), dim3(half, n_heads),
+                         dim3(kLongWaves * 64), 0, s, q, (bf16_t*)out, items + half, counts + 1, hidden,
+                         out_inv_scale);
     }
     return;
   }

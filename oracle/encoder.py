@@ -23,10 +23,11 @@ a linear token-classification head.  In order:
 Everything is float64 ("pure").  A second reading, "bf16", rounds to
 bfloat16 at exactly the points where the GPU's BF16 path stores a value:
 both operands of every GEMM, the stored hidden state after each LayerNorm
-(which is also the residual input of the next sublayer), Q/K/V, the attention
-probabilities before they multiply V, the attention output, and the GELU
-output.  Sums, LayerNorm statistics, the softmax max/sum and the classifier
-stay float64 (FP32 on the GPU).  "fp8" additionally rounds the inputs of the
+(which is also the residual input of the next sublayer), the residual sum
+x + sublayer(x) that each LayerNorm reads, Q/K/V, the attention
+probabilities (exp(s - row max)) before they multiply V, the attention
+output, and the GELU output.  Dot products, LayerNorm statistics, the softmax
+max/sum and the classifier stay float64 (FP32 on the GPU).  "fp8" additionally rounds the inputs of the
 QKV, output-projection, FFN1 and FFN2 GEMMs to FP8-E4M3 with static
 power-of-two per-tensor scales.
 """
@@ -146,11 +147,11 @@ def encoder_layer(W, cfg, l: int, x: np.ndarray, cu_seqlens: np.ndarray, prec: P
         A[a:b] = attention(qkv[a:b, :h].reshape(L, H, d), qkv[a:b, h:2 * h].reshape(L, H, d),
                            qkv[a:b, 2 * h:].reshape(L, H, d), rp).reshape(L, h)
     A = prec.store(A)
-    y = x + prec.gemm_in(A, l, 1) @ prec.gemm_w(_w(W, p + "wo")) + _w(W, p + "bo")
+    y = prec.store(x + prec.gemm_in(A, l, 1) @ prec.gemm_w(_w(W, p + "wo")) + _w(W, p + "bo"))
     x = prec.store(layer_norm(y, _w(W, p + "ln1_g"), _w(W, p + "ln1_b"), cfg.ln_eps))
     x_mid = x
     g = prec.store(gelu(prec.gemm_in(x, l, 2) @ prec.gemm_w(_w(W, p + "w1")) + _w(W, p + "b1")))
-    y = x + prec.gemm_in(g, l, 3) @ prec.gemm_w(_w(W, p + "w2")) + _w(W, p + "b2")
+    y = prec.store(x + prec.gemm_in(g, l, 3) @ prec.gemm_w(_w(W, p + "w2")) + _w(W, p + "b2"))
     x = prec.store(layer_norm(y, _w(W, p + "ln2_g"), _w(W, p + "ln2_b"), cfg.ln_eps))
     if taps is not None:
         taps[l] = dict(qkv=qkv, attn=A, ffn1=g, x_in=x_in, x_mid=x_mid)

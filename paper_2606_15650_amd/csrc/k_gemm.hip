@@ -323,9 +323,11 @@ bool dispatch_epi(const GemmParams& g, int ci, hipStream_t s) {
     if (sizeof(TI) == 4 && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GELU>(g, ci, s);
     if (sizeof(TI) == 2 && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GELU>(g, ci, s);
     if (sizeof(TI) == 1 && g.out == ET_FP8) return dispatch_tile<TI, fp8_t, float, EPI_GELU>(g, ci, s);
-  } else if (g.epi == EPI_RESID && g.out == ET_F32) {
-    if (sizeof(TI) == 4 && g.res == ET_F32) return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
-    if (sizeof(TI) != 4 && g.res == ET_BF16) return dispatch_tile<TI, float, bf16_t, EPI_RESID>(g, ci, s);
+  } else if (g.epi == EPI_RESID) {
+    if (sizeof(TI) == 4 && g.res == ET_F32 && g.out == ET_F32)
+      return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
+    if (sizeof(TI) != 4 && g.res == ET_BF16 && g.out == ET_BF16)
+      return dispatch_tile<TI, bf16_t, bf16_t, EPI_RESID>(g, ci, s);
   }
   return false;
 }

@@ -27,10 +27,53 @@ __device__ __forceinline__ int find_record(const int* cu, int B, int t) {
   return lo;
 }
 
+// A lane owns NPL elements of a row in chunks of VEC consecutive columns:
+// element i sits at column (i / VEC) * 64 * VEC + lane * VEC + i % VEC, so
+// every chunk is one 16-byte (fp32) or 8-byte (bf16) access and each wave
+// access covers a contiguous span of the row.
+template <int NPL>
+struct RowMap {
+  static constexpr int VEC = NPL % 4 == 0 ? 4 : NPL;
+  __device__ static int col(int i, int lane) { return (i / VEC) * 64 * VEC + lane * VEC + i % VEC; }
+};
+
+template <int NPL>
+__device__ __forceinline__ void load_row(const float* src, int lane, float (&v)[NPL]) {
+  typedef RowMap<NPL> RM;
+#pragma unroll
+  for (int c = 0; c < NPL / RM::VEC; ++c) {
+    if constexpr (RM::VEC == 4) {
+      const floatx4 x = *(const floatx4*)(src + RM::col(c * 4, lane));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[c * 4 + k] = x[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < RM::VEC; ++k) v[c * RM::VEC + k] = src[RM::col(c * RM::VEC + k, lane)];
+    }
+  }
+}
+
+template <int NPL>
+__device__ __forceinline__ void load_row(const bf16_t* src, int lane, float (&v)[NPL]) {
+  typedef RowMap<NPL> RM;
+#pragma unroll
+  for (int c = 0; c < NPL / RM::VEC; ++c) {
+    if constexpr (RM::VEC == 4) {
+      const bf16x4 x = *(const bf16x4*)(src + RM::col(c * 4, lane));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[c * 4 + k] = static_cast<float>(x[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < RM::VEC; ++k) v[c * RM::VEC + k] = static_cast<float>(src[RM::col(c * RM::VEC + k, lane)]);
+    }
+  }
+}
+
 template <int NPL>
 __device__ __forceinline__ void ln_store(float (&v)[NPL], const float* g, const float* b, float eps, int h,
                                          int lane, size_t row, void* out, ElemType out_t, fp8_t* out_q,
                                          float q_inv_scale) {
+  typedef RowMap<NPL> RM;
   float s = 0.f;
 #pragma unroll
   for (int i = 0; i < NPL; ++i) s += v[i];
@@ -44,14 +87,29 @@ __device__ __forceinline__ void ln_store(float (&v)[NPL], const float* g, const 
   const float var = wave_sum(q) / (float)h;
   const float rstd = 1.0f / sqrtf(var + eps);
 #pragma unroll
-  for (int i = 0; i < NPL; ++i) {
-    const int c = lane + 64 * i;
-    const float y = g[c] * ((v[i] - mean) * rstd) + b[c];
-    if (out_t == ET_F32) ((float*)out)[row * h + c] = y;
-    else {
-      const bf16_t yb = static_cast<bf16_t>(y);
-      ((bf16_t*)out)[row * h + c] = yb;
-      if (out_q) out_q[row * h + c].v = f32_to_e4m3(static_cast<float>(yb) * q_inv_scale);
+  for (int c = 0; c < NPL / RM::VEC; ++c) {
+    float y[RM::VEC];
+    const int c0 = RM::col(c * RM::VEC, lane);
+#pragma unroll
+    for (int k = 0; k < RM::VEC; ++k) y[k] = g[c0 + k] * ((v[c * RM::VEC + k] - mean) * rstd) + b[c0 + k];
+    if (out_t == ET_F32) {
+#pragma unroll
+      for (int k = 0; k < RM::VEC; ++k) ((float*)out)[row * h + c0 + k] = y[k];
+    } else {
+      bf16_t yb[RM::VEC];
+#pragma unroll
+      for (int k = 0; k < RM::VEC; ++k) yb[k] = static_cast<bf16_t>(y[k]);
+      if constexpr (RM::VEC == 4) {
+        *(bf16x4*)((bf16_t*)out + row * h + c0) = bf16x4{yb[0], yb[1], yb[2], yb[3]};
+      } else {
+#pragma unroll
+        for (int k = 0; k < RM::VEC; ++k) ((bf16_t*)out)[row * h + c0 + k] = yb[k];
+      }
+      if (out_q) {
+#pragma unroll
+        for (int k = 0; k < RM::VEC; ++k)
+          out_q[row * h + c0 + k].v = f32_to_e4m3(static_cast<float>(yb[k]) * q_inv_scale);
+      }
     }
   }
 }
@@ -74,17 +132,16 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
   }
   const int r = find_record(cu, B, t);
   const int p = min(max(t - cu[r], 0), max_pos - 1);
-  float v[NPL];
+  float v[NPL], w[NPL];
+  load_row<NPL>(tok + (size_t)id * h, lane, v);
+  load_row<NPL>(pos + (size_t)p * h, lane, w);
 #pragma unroll
-  for (int i = 0; i < NPL; ++i) {
-    const int c = lane + 64 * i;
-    v[i] = tok[(size_t)id * h + c] + pos[(size_t)p * h + c];
-  }
+  for (int i = 0; i < NPL; ++i) v[i] += w[i];
   ln_store<NPL>(v, g, b, eps, h, lane, t, out, out_t, out_q, q_inv_scale);
 }
 
-template <int NPL>
-__global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict__ y, const float* __restrict__ g,
+template <typename TY, int NPL>
+__global__ __launch_bounds__(256) void layernorm_kernel(const TY* __restrict__ y, const float* __restrict__ g,
                                                         const float* __restrict__ b, float eps, int rows, void* out,
                                                         ElemType out_t, fp8_t* out_q, float q_inv_scale) {
   const int lane = threadIdx.x & 63;
@@ -92,8 +149,7 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float* __restrict_
   if (row >= rows) return;
   constexpr int h = NPL * 64;
   float v[NPL];
-#pragma unroll
-  for (int i = 0; i < NPL; ++i) v[i] = y[(size_t)row * h + lane + 64 * i];
+  load_row<NPL>(y + (size_t)row * h, lane, v);
   ln_store<NPL>(v, g, b, eps, h, lane, row, out, out_t, out_q, q_inv_scale);
 }
 
@@ -218,11 +274,16 @@ void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const 
                                              out_t, out_q, q_inv_scale, err));
 }
 
-void launch_layernorm(const float* y, const float* g, const float* b, float eps, int rows, int h, void* out,
-                      ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
+void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
+                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
   if (rows <= 0) return;
-  ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0, s, y, g,
-                                             b, eps, rows, out, out_t, out_q, q_inv_scale));
+  if (y_t == ET_F32) {
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0,
+                                               s, (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+  } else {
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0,
+                                               s, (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+  }
 }
 
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,

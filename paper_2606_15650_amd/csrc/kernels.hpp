@@ -45,8 +45,8 @@ void launch_attention(const void* qkv, void* out, const int4* items, int max_ite
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
                      const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
                      ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s);
-void launch_layernorm(const float* y, const float* g, const float* b, float eps, int rows, int h, void* out,
-                      ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s);
+void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
+                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s);
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
                        uint8_t* labels, float* logits, float* margin, hipStream_t s);
 void launch_to_f32(const void* x, ElemType t, float* out, int64_t n, hipStream_t s);

@@ -317,7 +317,7 @@ void anon_model_free(anon_model* m) {
 struct EncWs {
   void *x, *x2, *qkv, *attn, *ffn;
   fp8_t* xq;
-  float* y;
+  void* y;  // pre-LayerNorm residual sum (act type)
   int4* qblocks;
   int* nq;
   int max_q;
@@ -331,7 +331,7 @@ static void enc_layout(const anon_model* m, int T, int B, Carver& k, EncWs& w) {
   w.xq = m->gemm_t == ET_FP8 ? k.take<fp8_t>(T * h) : nullptr;
   w.qkv = k.take<uint8_t>(T * 3 * h * q);
   w.attn = k.take<uint8_t>(T * h * g);
-  w.y = k.take<float>(T * h);
+  w.y = k.take<uint8_t>(T * h * a);
   w.ffn = k.take<uint8_t>(T * f * g);
   w.max_q = attn_plan_items(m->qkv_t, m->cfg.max_pos, T, B);
   w.qblocks = k.take<int4>(w.max_q);
@@ -401,7 +401,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.resid = w.x;
     g.res = m->act_t;
     g.C = w.y;
-    g.out = ET_F32;
+    g.out = m->act_t;
     g.N = h;
     g.K = h;
     g.epi = EPI_RESID;
@@ -415,7 +415,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     }
     {
       ProfScope ps(KC_LN, s, 0.0);
-      launch_layernorm(w.y, L.ln1_g, L.ln1_b, c.ln_eps, T, h, w.x2, m->act_t, w.xq, fp8 ? 1.f / L.sa[2] : 1.f, s);
+      launch_layernorm(w.y, m->act_t, L.ln1_g, L.ln1_b, c.ln_eps, T, h, w.x2, m->act_t, w.xq, fp8 ? 1.f / L.sa[2] : 1.f, s);
     }
     // FFN1 + bias + GELU
     g.A = fp8 ? (const void*)w.xq : w.x2;
@@ -441,7 +441,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.resid = w.x2;
     g.res = m->act_t;
     g.C = w.y;
-    g.out = ET_F32;
+    g.out = m->act_t;
     g.N = h;
     g.K = f;
     g.epi = EPI_RESID;
@@ -455,7 +455,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     {
       ProfScope ps(KC_LN, s, 0.0);
       const float nxt = (fp8 && l + 1 < c.n_layers) ? 1.f / m->layers[l + 1].sa[0] : 1.f;
-      launch_layernorm(w.y, L.ln2_g, L.ln2_b, c.ln_eps, T, h, w.x, m->act_t, fp8 ? w.xq : nullptr, nxt, s);
+      launch_layernorm(w.y, m->act_t, L.ln2_g, L.ln2_b, c.ln_eps, T, h, w.x, m->act_t, fp8 ? w.xq : nullptr, nxt, s);
     }
   }
   ANON_HIP_CHECK(hipGetLastError());
@@ -555,13 +555,13 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
       g.W = L.wqkv, g.bias = L.bqkv, g.C = w.qkv, g.N = 3 * h, g.K = h, g.epi = EPI_BIAS, g.out = m->qkv_t;
     } else if (gi == 1) {
       g.A = w.attn, g.W = L.wo, g.bias = L.bo, g.resid = w.x, g.res = m->act_t, g.C = w.y, g.N = h, g.K = h;
-      g.epi = EPI_RESID, g.out = ET_F32;
+      g.epi = EPI_RESID, g.out = m->act_t;
     } else if (gi == 2) {
       g.A = fp8 ? (const void*)w.xq : w.x2;
       g.W = L.w1, g.bias = L.b1, g.C = w.ffn, g.N = f, g.K = h, g.epi = EPI_GELU, g.out = m->gemm_t;
     } else {
       g.A = w.ffn, g.W = L.w2, g.bias = L.b2, g.resid = w.x2, g.res = m->act_t, g.C = w.y, g.N = h, g.K = f;
-      g.epi = EPI_RESID, g.out = ET_F32;
+      g.epi = EPI_RESID, g.out = m->act_t;
     }
     float best = 1e30f;
     int best_c = -1;

@@ -67,7 +67,7 @@ WORKLOADS = {
         "base_fp32", BASE, 4096, ("lognormal", 5.2, 0.6, 16, 512), "fp32",
         notes="same workload as base_bf16 on the plain FP32 path"),
     "stream_bf16": Workload(
-        "stream_bf16", BASE, 70951, ("lognormal", 7.35, 0.6, 16, 16384), "bf16",
+        "stream_bf16", BASE, 70951, ("lognormal", 7.04, 0.6, 16, 16384), "bf16",
         zipf_pool=200_000, window=512, stride=448,
         notes="dataset-scale records windowed at 512 tokens with 64-token overlap"),
     "tiny_fp8": Workload(

@@ -252,6 +252,114 @@ def _one_record(rng, n_tok, types, pool, vocab):
     return text, ids, off, labels, spans
 
 
+def _tokenize_line(parts, types, vocab):
+    """Bytes, ids, offsets, labels and entity (type, begin, end) of one pool line."""
+    text = "".join(p for p, _ in parts).encode()
+    b, e = token_spans(text)
+    ids = piece_ids(text, b, e, vocab)
+    lab = np.zeros(len(b), np.uint8)
+    ent = None
+    pos = 0
+    for p, t in parts:
+        n = len(p.encode())
+        if t is not None:
+            inside = np.nonzero((b >= pos) & (e <= pos + n))[0]
+            ti = types.index(t) + 1
+            lab[inside[0]] = 2 * ti - 1
+            lab[inside[1:]] = 2 * ti
+            ent = (ti, pos, pos + n)
+        pos += n
+    return text, ids, np.stack([b, e], 1).astype(np.int32), lab, ent
+
+
+def generate_records_fast(n_records: int, lengths, n_types: int, vocab: int, seed: int,
+                          zipf_pool: int = 200_000, zipf_s: float = 1.1, text_pool: int = 20_000,
+                          p_entity: float = 0.15) -> RecordBatch:
+    """Dataset-scale records from pre-tokenized line pools (vectorized assembly).
+
+    Lines are either free-text lines (a pool of ``text_pool`` distinct lines)
+    or ``Field: entity`` lines whose entity is drawn with Zipf(s) popularity
+    from ``zipf_pool`` distinct entities.  A record takes lines in order until
+    it holds its target token count; the last line is cut at that token.
+    """
+    rng = np.random.default_rng(seed)
+    lens = draw_lengths(lengths, n_records, rng) if isinstance(lengths, tuple) else np.asarray(lengths, np.int64)
+    types = TYPE_NAMES_17[:n_types]
+    lines = []
+    for _ in range(text_pool):
+        name = _FIELDS_TEXT[int(rng.integers(len(_FIELDS_TEXT)))]
+        lines.append([(f"{name}: ", None), (_words(rng, 8, 22), None), (".", None)])
+    pool = EntityPool(types, zipf_pool, zipf_s, seed)
+    for t, e in pool.items:
+        parts = [(f"{_FIELD_OF[t][0]}: ", None), (e, t)]
+        if t == "PORT":
+            parts.append(("/tcp", None))
+        lines.append(parts)
+    tok = [_tokenize_line(p, types, vocab) for p in lines]
+    L_bytes = [t[0] for t in tok]
+    L_nb = np.array([len(b) for b in L_bytes], np.int64)
+    L_nt = np.array([len(t[1]) for t in tok], np.int64)
+    L_t0 = np.concatenate([[0], np.cumsum(L_nt)])
+    F_ids = np.concatenate([t[1] for t in tok])
+    F_off = np.concatenate([t[2] for t in tok])
+    F_lab = np.concatenate([t[3] for t in tok])
+    L_ent = np.array([t[4] if t[4] is not None else (0, 0, 0) for t in tok], np.int64)
+
+    # line stream: entity lines with probability p_entity (Zipf rank), else text lines
+    need = int(lens.sum() / max(1.0, L_nt.mean()) * 1.3) + 1024
+    kinds = rng.random(need) < p_entity
+    ranks = np.minimum(np.searchsorted(pool.cdf, rng.random(need), side="right"), zipf_pool - 1)
+    stream = np.where(kinds, text_pool + ranks, rng.integers(0, text_pool, need))
+    cum = np.concatenate([[0], np.cumsum(L_nt[stream])])
+    starts = np.empty(n_records, np.int64)
+    ends = np.empty(n_records, np.int64)
+    s = 0
+    for r in range(n_records):
+        e = int(np.searchsorted(cum, cum[s] + lens[r], side="left"))  # lines s..e-1 reach the target
+        if e >= len(cum):
+            raise RuntimeError("line stream too short")
+        starts[r], ends[r] = s, e
+        s = e
+    # line instances of every record
+    n_lines = ends - starts
+    inst = np.concatenate([stream[a:b] for a, b in zip(starts, ends)]) if n_records else np.zeros(0, np.int64)
+    inst_rec = np.repeat(np.arange(n_records), n_lines)
+    first = np.concatenate([[0], np.cumsum(n_lines)])[:-1]
+    # byte offset of each line inside its record (lines joined by "\n")
+    inst_nb = L_nb[inst] + 1
+    csum = np.cumsum(inst_nb) - inst_nb
+    inst_boff = csum - np.repeat(csum[first], n_lines)
+    # tokens: ragged gather of each line's tokens, then cut each record at its length
+    inst_nt = L_nt[inst]
+    tbase = np.cumsum(inst_nt) - inst_nt
+    total = int(inst_nt.sum())
+    src = np.repeat(L_t0[inst] - tbase, inst_nt) + np.arange(total)
+    t_rec = np.repeat(inst_rec, inst_nt)
+    t_shift = np.repeat(inst_boff, inst_nt)
+    rec_t0 = np.concatenate([[0], np.cumsum(np.bincount(inst_rec, weights=inst_nt, minlength=n_records))])[:-1]
+    t_idx = np.arange(total) - np.repeat(rec_t0.astype(np.int64), np.bincount(t_rec, minlength=n_records))
+    keep = t_idx < lens[t_rec]
+    ids = F_ids[src[keep]].astype(np.int32)
+    off = (F_off[src[keep]] + t_shift[keep, None]).astype(np.int32)
+    lab = F_lab[src[keep]].astype(np.uint8)
+    cu_t = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    cut = off[cu_t[1:] - 1, 1].astype(np.int64)  # end byte of each record's last token
+    texts = []
+    for r in range(n_records):
+        texts.append(b"\n".join(L_bytes[i] for i in stream[starts[r]:ends[r]])[: cut[r]])
+    cu_b = np.concatenate([[0], np.cumsum([len(t) for t in texts])]).astype(np.int64)
+    # gold spans of entity lines that survive the cut
+    ent = L_ent[inst]
+    has = ent[:, 0] > 0
+    sb = inst_boff + ent[:, 1]
+    se = np.minimum(inst_boff + ent[:, 2], cut[inst_rec])
+    ok = has & (sb < cut[inst_rec])
+    spans = np.stack([inst_rec[ok], ent[ok, 0], sb[ok], se[ok]], 1).astype(np.int64)
+    return RecordBatch(text=b"".join(texts), cu_bytes=cu_b, ids=ids, tok_off=off, cu_seqlens=cu_t,
+                       gold_labels=lab, gold_spans=spans.reshape(-1, 4), type_names=list(types),
+                       n_pool_draws=int(ok.sum()))
+
+
 def generate_records(n_records: int, lengths, n_types: int, vocab: int, seed: int,
                      zipf_pool: int = 0, zipf_s: float = 1.1) -> RecordBatch:
     """Generate ``n_records`` records; ``lengths`` is a spec tuple or an int array."""

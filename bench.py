@@ -224,6 +224,9 @@ def stream_bench(max_chunk_tokens: int = 2_000_000) -> dict:
             labels, _, _ = pl.ner(c, logits=False, margin=False, window=512, stride=448)
             spans, cu_spans, cap = pl.spans(c, labels)
             pl.pseudonymize(c, spans, cu_spans, cap)
+            if k % 8 == 0:
+                print(f"[stream] {'timed' if stream_pass else 'warm-up'} chunk {k + 1}/{len(chunks)}",
+                      file=sys.stderr, flush=True)
         return n_spans
 
     run(False)  # warm-up pass (fills the pseudonym table as a first pass would)

@@ -248,16 +248,14 @@ struct Cfg {
   X(0, 128, 128, 64, 2, 2, 2, "bf16_128x128x64_w2x2") \
   X(1, 256, 128, 64, 2, 2, 1, "bf16_256x128x64_w2x2") \
   X(2, 128, 256, 64, 2, 2, 1, "bf16_128x256x64_w2x2") \
-  X(3, 256, 256, 32, 2, 2, 1, "bf16_256x256x32_w2x2") \
-  X(4, 256, 256, 64, 2, 2, 1, "bf16_256x256x64_w2x2") \
-  X(5, 256, 128, 32, 2, 2, 2, "bf16_256x128x32_w2x2") \
-  X(6, 128, 256, 32, 2, 2, 2, "bf16_128x256x32_w2x2") \
-  X(7, 256, 256, 64, 4, 2, 2, "bf16_256x256x64_w4x2") \
-  X(8, 256, 256, 32, 4, 2, 2, "bf16_256x256x32_w4x2") \
-  X(9, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2") \
-  X(10, 256, 128, 32, 4, 2, 2, "bf16_256x128x32_w4x2") \
-  X(11, 128, 256, 32, 2, 4, 2, "bf16_128x256x32_w2x4") \
-  X(12, 256, 128, 64, 4, 2, 2, "bf16_256x128x64_w4x2")
+  X(3, 256, 256, 64, 2, 2, 1, "bf16_256x256x64_w2x2") \
+  X(4, 128, 256, 32, 2, 2, 2, "bf16_128x256x32_w2x2") \
+  X(5, 256, 256, 64, 4, 2, 2, "bf16_256x256x64_w4x2") \
+  X(6, 256, 256, 32, 4, 2, 2, "bf16_256x256x32_w4x2") \
+  X(7, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2") \
+  X(8, 256, 128, 32, 4, 2, 2, "bf16_256x128x32_w4x2") \
+  X(9, 128, 256, 32, 2, 4, 2, "bf16_128x256x32_w2x4") \
+  X(10, 256, 128, 64, 4, 2, 2, "bf16_256x128x64_w4x2")
 #define ANON_F32_CFGS(X)                        \
   X(0, 128, 128, 32, 2, 2, 2, "f32_128x128x32_w2x2") \
   X(1, 64, 64, 32, 2, 2, 2, "f32_64x64x32_w2x2")     \
@@ -266,9 +264,10 @@ struct Cfg {
 #define ANON_FP8_CFGS(X)                           \
   X(0, 128, 128, 128, 2, 2, 2, "fp8_128x128x128_w2x2") \
   X(1, 256, 128, 128, 2, 2, 1, "fp8_256x128x128_w2x2") \
-  X(2, 256, 256, 64, 2, 2, 1, "fp8_256x256x64_w2x2")   \
-  X(3, 128, 256, 128, 2, 2, 1, "fp8_128x256x128_w2x2") \
-  X(4, 256, 128, 64, 2, 2, 2, "fp8_256x128x64_w2x2")
+  X(2, 128, 256, 128, 2, 2, 1, "fp8_128x256x128_w2x2") \
+  X(3, 256, 256, 64, 4, 2, 2, "fp8_256x256x64_w4x2")   \
+  X(4, 256, 128, 128, 4, 2, 2, "fp8_256x128x128_w4x2") \
+  X(5, 128, 128, 64, 2, 2, 2, "fp8_128x128x64_w2x2")
 
 #define ANON_CFG_ROW(i, bm, bn, bk, wgm, wgn, occ, name) {bm, bn, bk, wgm, wgn, occ, name},
 const Cfg kCfgBF16[] = {ANON_BF16_CFGS(ANON_CFG_ROW)};
@@ -315,18 +314,20 @@ bool dispatch_tile(const GemmParams& g, int ci, hipStream_t s) {
 
 template <typename TI>
 bool dispatch_epi(const GemmParams& g, int ci, hipStream_t s) {
-  // Supported (epilogue, output, residual) combinations.
-  if (g.epi == EPI_BIAS) {
-    if (sizeof(TI) == 4 && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_BIAS>(g, ci, s);
-    if (sizeof(TI) != 4 && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_BIAS>(g, ci, s);
-  } else if (g.epi == EPI_GELU) {
-    if (sizeof(TI) == 4 && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GELU>(g, ci, s);
-    if (sizeof(TI) == 2 && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GELU>(g, ci, s);
-    if (sizeof(TI) == 1 && g.out == ET_FP8) return dispatch_tile<TI, fp8_t, float, EPI_GELU>(g, ci, s);
-  } else if (g.epi == EPI_RESID) {
-    if (sizeof(TI) == 4 && g.res == ET_F32 && g.out == ET_F32)
+  // Supported (epilogue, output, residual) combinations per input type.
+  if constexpr (sizeof(TI) == 4) {
+    if (g.epi == EPI_BIAS && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_BIAS>(g, ci, s);
+    if (g.epi == EPI_GELU && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GELU>(g, ci, s);
+    if (g.epi == EPI_RESID && g.res == ET_F32 && g.out == ET_F32)
       return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
-    if (sizeof(TI) != 4 && g.res == ET_BF16 && g.out == ET_BF16)
+  } else {
+    if (g.epi == EPI_BIAS && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_BIAS>(g, ci, s);
+    if constexpr (sizeof(TI) == 2) {
+      if (g.epi == EPI_GELU && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GELU>(g, ci, s);
+    } else {
+      if (g.epi == EPI_GELU && g.out == ET_FP8) return dispatch_tile<TI, fp8_t, float, EPI_GELU>(g, ci, s);
+    }
+    if (g.epi == EPI_RESID && g.res == ET_BF16 && g.out == ET_BF16)
       return dispatch_tile<TI, bf16_t, bf16_t, EPI_RESID>(g, ci, s);
   }
   return false;
@@ -359,7 +360,7 @@ bool launch_gemm(const GemmParams& g, hipStream_t s) {
     // default: the preferred tile of the type if it divides the shape, else
     // the first one that does
     const int n = gemm_num_configs(g.in);
-    const int pref = g.in == ET_BF16 ? 1 : 0;
+    const int pref = g.in == ET_BF16 ? 5 : 0;
     ci = gemm_config_fits(g.in, pref, g.N, g.K) ? pref : -1;
     for (int c = 0; c < n && ci < 0; ++c)
       if (gemm_config_fits(g.in, c, g.N, g.K)) ci = c;

@@ -73,6 +73,9 @@ WORKLOADS = {
     "tiny_fp8": Workload(
         "tiny_fp8", TINY, 64, ("uniform", 16, 128), "fp8", o_target=None,
         notes="the tiny encoder with FP8-E4M3 GEMMs (parity cases)"),
+    "large_bf16": Workload(
+        "large_bf16", LARGE, 16384, ("lognormal", 5.5, 0.7, 16, 512), "bf16",
+        notes="the 24-layer h1024 workload in BF16 (comparison for FP8)"),
     "large_fp8": Workload(
         "large_fp8", LARGE, 16384, ("lognormal", 5.5, 0.7, 16, 512), "fp8",
         notes="24-layer h1024 encoder with FP8-E4M3 GEMMs"),

@@ -360,7 +360,8 @@ bool launch_gemm(const GemmParams& g, hipStream_t s) {
     // default: the preferred tile of the type if it divides the shape, else
     // the first one that does
     const int n = gemm_num_configs(g.in);
-    const int pref = g.in == ET_BF16 ? 5 : 0;
+    // (the residual epilogue on 256-wide tiles runs out of registers)
+    const int pref = (g.in == ET_BF16 && g.epi != EPI_RESID) ? 5 : 0;
     ci = gemm_config_fits(g.in, pref, g.N, g.K) ? pref : -1;
     for (int c = 0; c < n && ci < 0; ++c)
       if (gemm_config_fits(g.in, c, g.N, g.K)) ci = c;

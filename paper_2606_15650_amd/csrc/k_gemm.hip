@@ -115,8 +115,19 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "tile/threads mismatch");
   static_assert(TM >= 1 && TN >= 1 && BK % MF::KI == 0, "bad tile");
 
-  __shared__ TI As[2][BM * LDK];
-  __shared__ TI Bs[2][BN * LDK];
+  // Epilogue staging (reuses the operand LDS once the K loop is done): each
+  // wave parks SR rows of its tile in row-major order, then writes them back
+  // with 16-byte row-contiguous accesses.  TS is the staged type: FP32 for
+  // the residual epilogue (the residual is added before rounding), else TO.
+  typedef typename std::conditional<EPI == EPI_RESID, float, TO>::type TS;
+  constexpr int OPND_BYTES = 2 * (BM + BN) * LDK * (int)sizeof(TI);
+  constexpr int SPAD = 16 / (int)sizeof(TS);
+  constexpr int SROW = WTN + SPAD;
+  constexpr int SR = (WGM * WGN * 32 * SROW * (int)sizeof(TS) <= OPND_BYTES) ? 32 : 16;
+  static_assert(WGM * WGN * SR * SROW * (int)sizeof(TS) <= OPND_BYTES, "epilogue staging does not fit");
+  __shared__ __align__(16) char smem[OPND_BYTES];
+  TI(*As)[BM * LDK] = reinterpret_cast<TI(*)[BM * LDK]>(smem);
+  TI(*Bs)[BN * LDK] = reinterpret_cast<TI(*)[BN * LDK]>(smem + 2 * BM * LDK * sizeof(TI));
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
@@ -205,37 +216,76 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   // Epilogue: lane owns column (lane & 31) of each 32x32 tile and rows
   // (r/4)*8 + (lane/32)*4 + r%4 of accumulator register r.
   TO* __restrict__ C = (TO*)p.C;
-  auto epilogue = [&](auto guarded) {
+  TS* stg = reinterpret_cast<TS*>(smem) + wave * SR * SROW;
+  const int wrow0 = m0 + wm * WTM, wcol0 = n0 + wn * WTN;
+  float bias[TN], qs[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + wn * WTN + j * 32 + (lane & 31);
-      const float bias = p.bias[col];
-      const float qs = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
+  for (int j = 0; j < TN; ++j) {
+    const int col = wcol0 + j * 32 + (lane & 31);
+    bias[j] = p.bias[col];
+    qs[j] = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
+  }
+  constexpr int CH = 16 / (int)sizeof(TS);  // staged elements per 16-byte chunk
+  constexpr int CPRS = WTN / CH;            // chunks per staged row
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
+  for (int i = 0; i < TM; ++i) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = m0 + wm * WTM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          if (!decltype(guarded)::value || row < M) {
-            float v = acc[i][j][r] * p.acc_scale + bias;
-            if (EPI == EPI_BIAS) {
-              v *= qs;
-            } else if (EPI == EPI_GELU) {
-              v = gelu_erf(v);
-              // FP8 output: the activation is a bf16 value first (as in the
-              // BF16 path), then scaled and rounded to E4M3
-              if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
-            } else {
-              v += ld((const TR*)p.resid + (size_t)row * N + col);
-            }
-            st(C + (size_t)row * N + col, v);
+    for (int pass = 0; pass < 32 / SR; ++pass) {
+      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int r = pass * (SR / 4); r < (pass + 1) * (SR / 4); ++r) {
+          const int rin = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3) - pass * SR;
+          float v = acc[i][j][r] * p.acc_scale + bias[j];
+          if (EPI == EPI_BIAS) {
+            v *= qs[j];
+          } else if (EPI == EPI_GELU) {
+            v = gelu_erf(v);
+            // FP8 output: the activation is a bf16 value first (as in the
+            // BF16 path), then scaled and rounded to E4M3
+            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
           }
+          st(stg + rin * SROW + j * 32 + (lane & 31), v);
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // 2. write the rows back with 16-byte (staged) chunks
+      for (int c = lane; c < SR * CPRS; c += 64) {
+        const int rr = c / CPRS, cc = c % CPRS;
+        const int grow = wrow0 + i * 32 + pass * SR + rr, gcol = wcol0 + cc * CH;
+        if (grow >= M) continue;
+        const TS* src = stg + rr * SROW + cc * CH;
+        if constexpr (EPI == EPI_RESID) {
+          // CH = 4 FP32 sums; add the residual, round once to the output type
+          const floatx4 s4 = *(const floatx4*)src;
+          const TR* rp = (const TR*)p.resid + (size_t)grow * N + gcol;
+          float rv[4];
+          if constexpr (sizeof(TR) == 2) {
+            const bf16x4 r4 = *(const bf16x4*)rp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rv[k] = static_cast<float>(r4[k]);
+          } else {
+            const floatx4 r4 = *(const floatx4*)rp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rv[k] = r4[k];
+          }
+          TO* dst = C + (size_t)grow * N + gcol;
+          if constexpr (sizeof(TO) == 2) {
+            *(bf16x4*)dst = bf16x4{static_cast<bf16_t>(s4[0] + rv[0]), static_cast<bf16_t>(s4[1] + rv[1]),
+                                   static_cast<bf16_t>(s4[2] + rv[2]), static_cast<bf16_t>(s4[3] + rv[3])};
+          } else {
+            *(floatx4*)dst = floatx4{s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
+          }
+        } else {
+          *(intx4*)(C + (size_t)grow * N + gcol) = *(const intx4*)src;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-  };
-  if (m0 + BM <= M) epilogue(std::false_type{});
-  else epilogue(std::true_type{});
+  }
 }
 
 struct Cfg {

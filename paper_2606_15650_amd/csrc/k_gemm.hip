@@ -231,11 +231,13 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int pass = 0; pass < 32 / SR; ++pass) {
-      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major
+      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major;
+      //    accumulator registers r hold rows (r/4)*8 + (lane/32)*4 + r%4, so
+      //    SR rows are the registers [pass*SR/2, (pass+1)*SR/2)
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
 #pragma unroll
-        for (int r = pass * (SR / 4); r < (pass + 1) * (SR / 4); ++r) {
+        for (int r = pass * (SR / 2); r < (pass + 1) * (SR / 2); ++r) {
           const int rin = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3) - pass * SR;
           float v = acc[i][j][r] * p.acc_scale + bias[j];
           if (EPI == EPI_BIAS) {

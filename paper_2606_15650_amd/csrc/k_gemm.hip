@@ -406,18 +406,20 @@ bool gemm_config_fits(ElemType in, int config, int N, int K) {
   return N % c[config].bn == 0 && K % c[config].bk == 0;
 }
 
+int default_gemm_config(const GemmParams& g) {
+  // the preferred tile of the type if it divides the shape, else the first
+  // one that does
+  const int n = gemm_num_configs(g.in);
+  const int pref = g.in == ET_BF16 ? 5 : (g.in == ET_FP8 ? 3 : 0);
+  if (gemm_config_fits(g.in, pref, g.N, g.K)) return pref;
+  for (int c = 0; c < n; ++c)
+    if (gemm_config_fits(g.in, c, g.N, g.K)) return c;
+  return -1;
+}
+
 bool launch_gemm(const GemmParams& g, hipStream_t s) {
   int ci = g.config;
-  if (ci < 0) {
-    // default: the preferred tile of the type if it divides the shape, else
-    // the first one that does
-    const int n = gemm_num_configs(g.in);
-    // (the residual epilogue on 256-wide tiles runs out of registers)
-    const int pref = (g.in == ET_BF16 && g.epi != EPI_RESID) ? 5 : 0;
-    ci = gemm_config_fits(g.in, pref, g.N, g.K) ? pref : -1;
-    for (int c = 0; c < n && ci < 0; ++c)
-      if (gemm_config_fits(g.in, c, g.N, g.K)) ci = c;
-  }
+  if (ci < 0) ci = default_gemm_config(g);
   if (ci < 0 || !gemm_config_fits(g.in, ci, g.N, g.K)) {
     set_error(ANON_EINVAL, "gemm: no tile configuration divides N=" + std::to_string(g.N) + " K=" +
                                std::to_string(g.K));

@@ -26,6 +26,7 @@ struct GemmParams {
 };
 // Returns false (and sets the error) if no kernel matches the shapes/types.
 bool launch_gemm(const GemmParams& p, hipStream_t s);
+int default_gemm_config(const GemmParams& p);
 int gemm_num_configs(ElemType in);
 const char* gemm_config_name(ElemType in, int config);
 bool gemm_config_fits(ElemType in, int config, int N, int K);

@@ -7,11 +7,11 @@
 //   fp32: v_mfma_f32_32x32x2_f32      (K step 2)
 //   bf16: v_mfma_f32_32x32x16_bf16    (K step 16)
 //   fp8 : v_mfma_scale_f32_32x32x64_f8f6f4 with E4M3 operands (K step 64)
-// A and W tiles are staged through double-buffered, row-padded LDS (16 bytes
-// of padding per row keeps the 16-byte fragment reads of 16 lanes on distinct
-// banks).  The next K tile is fetched into registers while the current one is
-// multiplied, and the MFMA operands of k-step s+1 are read from LDS while the
-// MFMAs of step s run.
+// Two main loops: BF16/FP8 operands stream global -> LDS directly through a
+// ring of ST K tiles (global_load_lds_dwordx4, XOR-swizzled rows); FP32
+// operands go through registers into double-buffered, padded LDS.  In both
+// the MFMA operands of k-step s+1 are read from LDS while those of step s
+// are multiplied.
 //
 // The K loop always runs in increasing k with one MFMA shape per precision,
 // so each output element's sum is formed in the same order whatever the tile
@@ -19,7 +19,10 @@
 // configurations are interchangeable bit for bit).
 //
 // Epilogues: bias (+ exact scaling of the Q columns by 1/sqrt(d)); bias + GELU;
-// bias + residual into an FP32 pre-LayerNorm buffer.
+// bias + residual added in FP32 and rounded once to the output type.
+#include <algorithm>
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace anon {
@@ -87,6 +90,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return x * per + min(x, rem) + loc;
 }
 
+// Linear tile index -> (row block, column block), in groups of `gm` row
+// blocks walked column by column: the tiles in flight on one XCD then share
+// a few A row blocks and a few weight column panels, a working set that fits
+// its L2, instead of cycling through the whole weight matrix per row block.
+__device__ __forceinline__ void group_tile(int t, int ntm, int ntn, int gm, int& mb, int& nb) {
+  const int per_group = gm * ntn;
+  const int g = t / per_group, r = t - g * per_group;
+  const int m0 = g * gm, gsz = min(ntm - m0, gm);
+  mb = m0 + r % gsz;
+  nb = r / gsz;
+}
+
 struct DevParams {
   const void* A;
   const void* W;
@@ -98,8 +113,118 @@ struct DevParams {
   int qcols;
   float acc_scale;
   float out_inv_scale;
+  int group_m;
+  int nt_store;
 };
 
+// Epilogue staging: once the K loop is done, the operand LDS is reused and
+// each wave parks SR rows of its tile in row-major order, then writes them
+// back with 16-byte row-contiguous accesses.  TS is the staged type: FP32 for
+// the residual epilogue (the residual is added before rounding), else TO.
+template <typename TO, int EPI, int BN_W, int NW, int SMEM>
+struct Staging {
+  typedef typename std::conditional<EPI == EPI_RESID, float, TO>::type TS;
+  static constexpr int SPAD = 16 / (int)sizeof(TS);
+  static constexpr int SROW = BN_W + SPAD;
+  static constexpr int SR = (NW * 32 * SROW * (int)sizeof(TS) <= SMEM) ? 32 : 16;
+  static_assert(NW * SR * SROW * (int)sizeof(TS) <= SMEM, "epilogue staging does not fit");
+};
+
+// Applies the epilogue to a wave's (TM*32) x (TN*32) accumulator block whose
+// top-left output element is (wrow0, wcol0).  Lane owns column (lane & 31) of
+// each 32x32 tile and rows (r/4)*8 + (lane/32)*4 + r%4 of register r.
+template <typename TO, typename TR, int EPI, int TM, int TN, int NW, int SMEM>
+__device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM][TN], char* smem, int wave, int lane,
+                                         int wrow0, int wcol0) {
+  constexpr int WTN = TN * 32;
+  typedef Staging<TO, EPI, WTN, NW, SMEM> SG;
+  typedef typename SG::TS TS;
+  constexpr int SR = SG::SR, SROW = SG::SROW;
+  const int M = p.M, N = p.N;
+  TO* __restrict__ C = (TO*)p.C;
+  TS* stg = reinterpret_cast<TS*>(smem) + wave * SR * SROW;
+  float bias[TN], qs[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = wcol0 + j * 32 + (lane & 31);
+    bias[j] = p.bias[col];
+    qs[j] = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
+  }
+  constexpr int CH = 16 / (int)sizeof(TS);  // staged elements per 16-byte chunk
+  constexpr int CPRS = WTN / CH;            // chunks per staged row
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int pass = 0; pass < 32 / SR; ++pass) {
+      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major;
+      //    accumulator registers r hold rows (r/4)*8 + (lane/32)*4 + r%4, so
+      //    SR rows are the registers [pass*SR/2, (pass+1)*SR/2)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int r = pass * (SR / 2); r < (pass + 1) * (SR / 2); ++r) {
+          const int rin = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3) - pass * SR;
+          float v = acc[i][j][r] * p.acc_scale + bias[j];
+          if (EPI == EPI_BIAS) {
+            v *= qs[j];
+          } else if (EPI == EPI_GELU) {
+            v = gelu_erf(v);
+            // FP8 output: the activation is a bf16 value first (as in the
+            // BF16 path), then scaled and rounded to E4M3
+            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
+          }
+          st(stg + rin * SROW + j * 32 + (lane & 31), v);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // 2. write the rows back with 16-byte (staged) chunks
+      for (int c = lane; c < SR * CPRS; c += 64) {
+        const int rr = c / CPRS, cc = c % CPRS;
+        const int grow = wrow0 + i * 32 + pass * SR + rr, gcol = wcol0 + cc * CH;
+        if (grow >= M) continue;
+        const TS* src = stg + rr * SROW + cc * CH;
+        if constexpr (EPI == EPI_RESID) {
+          // CH = 4 FP32 sums; add the residual, round once to the output type
+          const floatx4 s4 = *(const floatx4*)src;
+          const TR* rp = (const TR*)p.resid + (size_t)grow * N + gcol;
+          float rv[4];
+          if constexpr (sizeof(TR) == 2) {
+            const bf16x4 r4 = *(const bf16x4*)rp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rv[k] = static_cast<float>(r4[k]);
+          } else {
+            const floatx4 r4 = *(const floatx4*)rp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rv[k] = r4[k];
+          }
+          TO* dst = C + (size_t)grow * N + gcol;
+          if constexpr (sizeof(TO) == 2) {
+            const bf16x4 o = bf16x4{static_cast<bf16_t>(s4[0] + rv[0]), static_cast<bf16_t>(s4[1] + rv[1]),
+                                    static_cast<bf16_t>(s4[2] + rv[2]), static_cast<bf16_t>(s4[3] + rv[3])};
+            if (p.nt_store) __builtin_nontemporal_store(o, (bf16x4*)dst);
+            else *(bf16x4*)dst = o;
+          } else {
+            const floatx4 o = floatx4{s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
+            if (p.nt_store) __builtin_nontemporal_store(o, (floatx4*)dst);
+            else *(floatx4*)dst = o;
+          }
+        } else {
+          const intx4 o = *(const intx4*)src;
+          if (p.nt_store) __builtin_nontemporal_store(o, (intx4*)(C + (size_t)grow * N + gcol));
+          else *(intx4*)(C + (size_t)grow * N + gcol) = o;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+}
+
+// Register-staged kernel (FP32 operands): the next K tile is fetched into
+// registers while the current one is multiplied from double-buffered,
+// row-padded LDS (16 bytes of padding per row keeps the 16-byte fragment
+// reads of 16 lanes on distinct banks).
 template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int OCC>
 __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   typedef Mfma<TI> MF;
@@ -114,17 +239,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   constexpr int NKS = BK / MF::KI;
   static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "tile/threads mismatch");
   static_assert(TM >= 1 && TN >= 1 && BK % MF::KI == 0, "bad tile");
-
-  // Epilogue staging (reuses the operand LDS once the K loop is done): each
-  // wave parks SR rows of its tile in row-major order, then writes them back
-  // with 16-byte row-contiguous accesses.  TS is the staged type: FP32 for
-  // the residual epilogue (the residual is added before rounding), else TO.
-  typedef typename std::conditional<EPI == EPI_RESID, float, TO>::type TS;
   constexpr int OPND_BYTES = 2 * (BM + BN) * LDK * (int)sizeof(TI);
-  constexpr int SPAD = 16 / (int)sizeof(TS);
-  constexpr int SROW = WTN + SPAD;
-  constexpr int SR = (WGM * WGN * 32 * SROW * (int)sizeof(TS) <= OPND_BYTES) ? 32 : 16;
-  static_assert(WGM * WGN * SR * SROW * (int)sizeof(TS) <= OPND_BYTES, "epilogue staging does not fit");
   __shared__ __align__(16) char smem[OPND_BYTES];
   TI(*As)[BM * LDK] = reinterpret_cast<TI(*)[BM * LDK]>(smem);
   TI(*Bs)[BN * LDK] = reinterpret_cast<TI(*)[BN * LDK]>(smem + 2 * BM * LDK * sizeof(TI));
@@ -134,8 +249,9 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
   const int M = p.M, N = p.N, K = p.K;
   const int ntn = N / BN;
   const int ntm = (M + BM - 1) / BM;
-  const int tile = xcd_remap(blockIdx.x, ntm * ntn);
-  const int m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+  int mb, nb;
+  group_tile(xcd_remap(blockIdx.x, ntm * ntn), ntm, ntn, p.group_m, mb, nb);
+  const int m0 = mb * BM, n0 = nb * BN;
 
   const TI* __restrict__ A = (const TI*)p.A;
   const TI* __restrict__ W = (const TI*)p.W;
@@ -212,116 +328,239 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
     if (kt + 1 < KT) lstore(buf ^ 1);
     __syncthreads();
   }
+  epilogue<TO, TR, EPI, TM, TN, WGM * WGN, OPND_BYTES>(p, acc, smem, wave, lane, m0 + wm * WTM, n0 + wn * WTN);
+}
 
-  // Epilogue: lane owns column (lane & 31) of each 32x32 tile and rows
-  // (r/4)*8 + (lane/32)*4 + r%4 of accumulator register r.
-  TO* __restrict__ C = (TO*)p.C;
-  TS* stg = reinterpret_cast<TS*>(smem) + wave * SR * SROW;
-  const int wrow0 = m0 + wm * WTM, wcol0 = n0 + wn * WTN;
-  float bias[TN], qs[TN];
+// LDS-ring kernel (BF16 / FP8 operands).  Each K tile travels from global
+// memory straight into LDS (global_load_lds_dwordx4: no register staging),
+// ST tiles deep, so the loads of tile k+ST-1 are in flight while tile k is
+// multiplied.  One barrier per K tile: after it, every wave's copy of tile k
+// has landed and every wave has finished reading tile k-1, whose slot then
+// takes tile k+ST-1.
+//
+// LDS layout: rows of BK elements, unpadded, with the 16-byte chunks of a
+// row XOR-permuted by a function of the row (chunk c of row r sits in slot
+// c ^ swz(r)): a 16-lane group reading the same logical chunk of 16
+// consecutive rows then touches 16 distinct 16-byte bank groups, and one
+// wave's load instruction fills 1024 contiguous bytes.
+template <int CPR>
+__device__ __forceinline__ int lds_swz(int r) {
+  static_assert(CPR == 4 || CPR == 8, "rows of 64 or 128 bytes");
+  return CPR == 8 ? (r >> 1) & 7 : (r >> 2) & 3;
+}
+
+__device__ __forceinline__ void dma16(const void* g, char* l) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                   (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(n) alone (expcnt and lgkmcnt left at their maxima)
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST,
+          int OCC>
+__global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams p) {
+  typedef Mfma<TI> MF;
+  typedef typename MF::frag frag;
+  constexpr int NW = WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TM = WTM / 32, TN = WTN / 32;
+  constexpr int EPC = 16 / (int)sizeof(TI);    // elements per 16-byte chunk
+  constexpr int CPR = BK / EPC;                // chunks per row
+  constexpr int ROWB = BK * (int)sizeof(TI);   // bytes per row
+  constexpr int RPI = 64 / CPR;                // rows per wave load instruction
+  constexpr int A_INS = BM / RPI / NW, B_INS = BN / RPI / NW;
+  constexpr int LPT = A_INS + B_INS;           // load instructions per wave per K tile
+  constexpr int A_BYTES = BM * ROWB, STAGE = (BM + BN) * ROWB;
+  constexpr int NKS = BK / MF::KI;             // MFMA k-steps per K tile
+  constexpr int NCH = MF::KPL * (int)sizeof(TI) / 16;  // chunks per lane fragment
+  constexpr int CPS = MF::KI / EPC;            // chunks per k-step
+  static_assert(BM % (RPI * NW) == 0 && BN % (RPI * NW) == 0, "tile/waves mismatch");
+  static_assert(TM >= 1 && TN >= 1 && BK % MF::KI == 0 && ST >= 2, "bad tile");
+  static_assert((ST - 1) * LPT < 64, "vmcnt range");
+  constexpr int SMEM = ST * STAGE;
+  static_assert(SMEM <= 160 * 1024, "LDS ring exceeds the CU's 160 KB");
+  __shared__ __align__(1024) char smem[SMEM];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int M = p.M, N = p.N, K = p.K;
+  const int ntn = N / BN;
+  const int ntm = (M + BM - 1) / BM;
+  int mb, nb;
+  group_tile(xcd_remap(blockIdx.x, ntm * ntn), ntm, ntn, p.group_m, mb, nb);
+  const int m0 = mb * BM, n0 = nb * BN;
+
+  // this lane's source of each load instruction at k = 0 (rows past M, in
+  // the last row block only, re-read row M-1: never stored, no branch)
+  const TI* ga[A_INS];
+  const TI* gb[B_INS];
+  {
+    const int rl = lane / CPR, slot = lane % CPR;
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int col = wcol0 + j * 32 + (lane & 31);
-    bias[j] = p.bias[col];
-    qs[j] = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
-  }
-  constexpr int CH = 16 / (int)sizeof(TS);  // staged elements per 16-byte chunk
-  constexpr int CPRS = WTN / CH;            // chunks per staged row
+    for (int i = 0; i < A_INS; ++i) {
+      const int r = (wave * A_INS + i) * RPI + rl;
+      ga[i] = (const TI*)p.A + (size_t)min(m0 + r, M - 1) * K + (slot ^ lds_swz<CPR>(r)) * EPC;
+    }
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-#pragma unroll
-    for (int pass = 0; pass < 32 / SR; ++pass) {
-      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major;
-      //    accumulator registers r hold rows (r/4)*8 + (lane/32)*4 + r%4, so
-      //    SR rows are the registers [pass*SR/2, (pass+1)*SR/2)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-#pragma unroll
-        for (int r = pass * (SR / 2); r < (pass + 1) * (SR / 2); ++r) {
-          const int rin = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3) - pass * SR;
-          float v = acc[i][j][r] * p.acc_scale + bias[j];
-          if (EPI == EPI_BIAS) {
-            v *= qs[j];
-          } else if (EPI == EPI_GELU) {
-            v = gelu_erf(v);
-            // FP8 output: the activation is a bf16 value first (as in the
-            // BF16 path), then scaled and rounded to E4M3
-            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
-          }
-          st(stg + rin * SROW + j * 32 + (lane & 31), v);
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      // 2. write the rows back with 16-byte (staged) chunks
-      for (int c = lane; c < SR * CPRS; c += 64) {
-        const int rr = c / CPRS, cc = c % CPRS;
-        const int grow = wrow0 + i * 32 + pass * SR + rr, gcol = wcol0 + cc * CH;
-        if (grow >= M) continue;
-        const TS* src = stg + rr * SROW + cc * CH;
-        if constexpr (EPI == EPI_RESID) {
-          // CH = 4 FP32 sums; add the residual, round once to the output type
-          const floatx4 s4 = *(const floatx4*)src;
-          const TR* rp = (const TR*)p.resid + (size_t)grow * N + gcol;
-          float rv[4];
-          if constexpr (sizeof(TR) == 2) {
-            const bf16x4 r4 = *(const bf16x4*)rp;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rv[k] = static_cast<float>(r4[k]);
-          } else {
-            const floatx4 r4 = *(const floatx4*)rp;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rv[k] = r4[k];
-          }
-          TO* dst = C + (size_t)grow * N + gcol;
-          if constexpr (sizeof(TO) == 2) {
-            *(bf16x4*)dst = bf16x4{static_cast<bf16_t>(s4[0] + rv[0]), static_cast<bf16_t>(s4[1] + rv[1]),
-                                   static_cast<bf16_t>(s4[2] + rv[2]), static_cast<bf16_t>(s4[3] + rv[3])};
-          } else {
-            *(floatx4*)dst = floatx4{s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
-          }
-        } else {
-          *(intx4*)(C + (size_t)grow * N + gcol) = *(const intx4*)src;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int i = 0; i < B_INS; ++i) {
+      const int r = (wave * B_INS + i) * RPI + rl;
+      gb[i] = (const TI*)p.W + (size_t)(n0 + r) * K + (slot ^ lds_swz<CPR>(r)) * EPC;
     }
   }
+  auto issue = [&](int kt, int stage) {
+    char* sa = smem + stage * STAGE + wave * A_INS * 1024;
+    char* sb = smem + stage * STAGE + A_BYTES + wave * B_INS * 1024;
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < A_INS; ++i) dma16(ga[i] + k0, sa + i * 1024);
+#pragma unroll
+    for (int i = 0; i < B_INS; ++i) dma16(gb[i] + k0, sb + i * 1024);
+  };
+
+  // fragment addresses: row (lane & 31) of each 32-row sub-tile; the swizzle
+  // is the same for rows 32 apart, so one slot offset per (k-step, chunk)
+  const int ra = wm * WTM + (lane & 31), rb = wn * WTN + (lane & 31);
+  int aoff[NKS][NCH], boff[NKS][NCH];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const int kc = ks * CPS + (lane >> 5) * NCH + q;
+      aoff[ks][q] = ra * ROWB + (kc ^ lds_swz<CPR>(ra)) * 16;
+      boff[ks][q] = A_BYTES + rb * ROWB + (kc ^ lds_swz<CPR>(rb)) * 16;
+    }
+  auto rdfrag = [&](const char* base, const int (&off)[NCH], int sub) {
+    frag f;
+    if constexpr (NCH == 1) {
+      f = *(const frag*)(base + off[0] + sub * 32 * ROWB);
+    } else {
+      const intx4 lo = *(const intx4*)(base + off[0] + sub * 32 * ROWB);
+      const intx4 hi = *(const intx4*)(base + off[1] + sub * 32 * ROWB);
+      f = frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+    return f;
+  };
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int KT = K / BK;
+  // The ring always holds ST tiles in flight or resident; refills past the
+  // last tile re-read tile KT-1 (valid memory, never multiplied), so the loop
+  // body has no data-dependent branches and the wait counts are constants.
+#pragma unroll
+  for (int s = 0; s < ST; ++s) issue(min(s, KT - 1), s);
+  wait_vmcnt<(ST - 1) * LPT>();
+  __builtin_amdgcn_s_barrier();
+
+  // Fragments are double-buffered across k-steps, also across tiles: the
+  // buffer of a k-step is the parity of its global k-step index, a
+  // compile-time value once the tile loop is unrolled by two.
+  frag fa[2][TM], fb[2][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) fa[0][i] = rdfrag(smem, aoff[0], i);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) fb[0][j] = rdfrag(smem, boff[0], j);
+  int stage = 0;
+  // One K tile.  During its last k-step the next tile is made ready: wait for
+  // it, barrier (every wave has then also finished reading this tile, whose
+  // slot takes tile kt+ST), and read its first fragments while this tile's
+  // last MFMAs run.
+  auto tile_body = [&](int kt, auto tpar) {
+    constexpr int TP = decltype(tpar)::value;
+    const char* base = smem + stage * STAGE;
+    const int nstage = stage + 1 == ST ? 0 : stage + 1;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int cur = (TP * NKS + ks) & 1;
+      if (ks + 1 < NKS) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) fa[cur ^ 1][i] = rdfrag(base, aoff[ks + 1 < NKS ? ks + 1 : 0], i);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) fb[cur ^ 1][j] = rdfrag(base, boff[ks + 1 < NKS ? ks + 1 : 0], j);
+      } else {
+        // this wave's reads of the tile have returned before anyone may
+        // overwrite it; tile kt+1 has landed for this wave
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) (vmcnt, expcnt at maxima)
+        wait_vmcnt<(ST - 2) * LPT>();
+        __builtin_amdgcn_s_barrier();
+        issue(min(kt + ST, KT - 1), stage);
+        const char* nbase = smem + nstage * STAGE;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) fa[cur ^ 1][i] = rdfrag(nbase, aoff[0], i);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) fb[cur ^ 1][j] = rdfrag(nbase, boff[0], j);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[cur][i], fb[cur][j], acc[i][j]);
+    }
+    stage = nstage;
+  };
+  for (int kt = 0; kt < KT; kt += 2) {
+    tile_body(kt, std::integral_constant<int, 0>());
+    if (kt + 1 < KT) tile_body(kt + 1, std::integral_constant<int, 1>());
+  }
+  // the refills issued by the last tiles must land before the staging below
+  // reuses the ring
+  wait_vmcnt<0>();
+  // and every wave must have finished reading it
+  __syncthreads();
+  epilogue<TO, TR, EPI, TM, TN, NW, SMEM>(p, acc, smem, wave, lane, m0 + wm * WTM, n0 + wn * WTN);
+}
+
+int env_int(const char* name, int def) {
+  const char* v = getenv(name);
+  return v && *v ? atoi(v) : def;
 }
 
 struct Cfg {
-  int bm, bn, bk, wgm, wgn, occ;
+  int bm, bn, bk, wgm, wgn, st, occ;
   const char* name;
 };
 
 // Tile configurations per input type; index = GemmParams::config.
-#define ANON_BF16_CFGS(X)                          \
-  X(0, 128, 128, 64, 2, 2, 2, "bf16_128x128x64_w2x2") \
-  X(1, 256, 128, 64, 2, 2, 1, "bf16_256x128x64_w2x2") \
-  X(2, 128, 256, 64, 2, 2, 1, "bf16_128x256x64_w2x2") \
-  X(3, 256, 256, 64, 2, 2, 1, "bf16_256x256x64_w2x2") \
-  X(4, 128, 256, 32, 2, 2, 2, "bf16_128x256x32_w2x2") \
-  X(5, 256, 256, 64, 4, 2, 2, "bf16_256x256x64_w4x2") \
-  X(6, 256, 256, 32, 4, 2, 2, "bf16_256x256x32_w4x2") \
-  X(7, 128, 128, 32, 2, 2, 2, "bf16_128x128x32_w2x2") \
-  X(8, 256, 128, 32, 4, 2, 2, "bf16_256x128x32_w4x2") \
-  X(9, 128, 256, 32, 2, 4, 2, "bf16_128x256x32_w2x4") \
-  X(10, 256, 128, 64, 4, 2, 2, "bf16_256x128x64_w4x2")
-#define ANON_F32_CFGS(X)                        \
-  X(0, 128, 128, 32, 2, 2, 2, "f32_128x128x32_w2x2") \
-  X(1, 64, 64, 32, 2, 2, 2, "f32_64x64x32_w2x2")     \
-  X(2, 128, 128, 16, 2, 2, 2, "f32_128x128x16_w2x2") \
-  X(3, 256, 128, 16, 2, 2, 1, "f32_256x128x16_w2x2")
-#define ANON_FP8_CFGS(X)                           \
-  X(0, 128, 128, 128, 2, 2, 2, "fp8_128x128x128_w2x2") \
-  X(1, 256, 128, 128, 2, 2, 1, "fp8_256x128x128_w2x2") \
-  X(2, 128, 256, 128, 2, 2, 1, "fp8_128x256x128_w2x2") \
-  X(3, 256, 256, 64, 4, 2, 2, "fp8_256x256x64_w4x2")   \
-  X(4, 256, 128, 128, 4, 2, 2, "fp8_256x128x128_w4x2") \
-  X(5, 128, 128, 64, 2, 2, 2, "fp8_128x128x64_w2x2")
+// Columns: BM, BN, BK, wave grid WGM x WGN, LDS ring stages (0: the
+// register-staged kernel), workgroups per CU the registers are sized for.
+#define ANON_BF16_CFGS(X)                                      \
+  X(0, 256, 256, 64, 4, 2, 0, 2, "bf16_256x256x64_w4x2")       \
+  X(1, 256, 128, 32, 4, 2, 0, 2, "bf16_256x128x32_w4x2")       \
+  X(2, 128, 256, 32, 2, 4, 0, 2, "bf16_128x256x32_w2x4")       \
+  X(3, 256, 256, 32, 4, 2, 3, 1, "bf16_256x256x32_w4x2_s3")    \
+  X(4, 256, 128, 64, 4, 2, 3, 1, "bf16_256x128x64_w4x2_s3")    \
+  X(5, 128, 256, 64, 2, 4, 3, 1, "bf16_128x256x64_w2x4_s3")    \
+  X(6, 256, 128, 32, 4, 2, 3, 2, "bf16_256x128x32_w4x2_s3")    \
+  X(7, 128, 256, 32, 2, 4, 3, 2, "bf16_128x256x32_w2x4_s3")    \
+  X(8, 256, 256, 64, 4, 2, 2, 1, "bf16_256x256x64_w4x2_s2")    \
+  X(9, 256, 256, 32, 4, 2, 4, 1, "bf16_256x256x32_w4x2_s4")    \
+  X(10, 256, 128, 32, 4, 2, 4, 1, "bf16_256x128x32_w4x2_s4")
+#define ANON_F32_CFGS(X)                                 \
+  X(0, 128, 128, 32, 2, 2, 0, 2, "f32_128x128x32_w2x2") \
+  X(1, 64, 64, 32, 2, 2, 0, 2, "f32_64x64x32_w2x2")     \
+  X(2, 128, 128, 16, 2, 2, 0, 2, "f32_128x128x16_w2x2") \
+  X(3, 256, 128, 16, 2, 2, 0, 1, "f32_256x128x16_w2x2")
+#define ANON_FP8_CFGS(X)                                    \
+  X(0, 256, 256, 64, 4, 2, 0, 2, "fp8_256x256x64_w4x2")     \
+  X(1, 256, 256, 64, 4, 2, 3, 1, "fp8_256x256x64_w4x2_s3")  \
+  X(2, 256, 256, 128, 4, 2, 2, 1, "fp8_256x256x128_w4x2_s2") \
+  X(3, 256, 128, 128, 4, 2, 3, 1, "fp8_256x128x128_w4x2_s3") \
+  X(4, 256, 128, 64, 4, 2, 3, 2, "fp8_256x128x64_w4x2_s3")  \
+  X(5, 128, 256, 64, 2, 4, 3, 2, "fp8_128x256x64_w2x4_s3")  \
+  X(6, 256, 256, 64, 4, 2, 4, 1, "fp8_256x256x64_w4x2_s4")
 
-#define ANON_CFG_ROW(i, bm, bn, bk, wgm, wgn, occ, name) {bm, bn, bk, wgm, wgn, occ, name},
+#define ANON_CFG_ROW(i, bm, bn, bk, wgm, wgn, st, occ, name) {bm, bn, bk, wgm, wgn, st, occ, name},
 const Cfg kCfgBF16[] = {ANON_BF16_CFGS(ANON_CFG_ROW)};
 const Cfg kCfgF32[] = {ANON_F32_CFGS(ANON_CFG_ROW)};
 const Cfg kCfgFP8[] = {ANON_FP8_CFGS(ANON_CFG_ROW)};
@@ -339,17 +578,26 @@ const Cfg* cfgs(ElemType t, int* n) {
   return kCfgFP8;
 }
 
-template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int OCC>
+template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST, int OCC>
 void run(const GemmParams& g, hipStream_t s) {
-  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale};
+  static const int group_m = std::max(1, env_int("ANON_GEMM_GROUP_M", 1));
+  static const int nt_store = env_int("ANON_GEMM_NT", 0);
+  DevParams p{g.A,      g.W,      g.bias,          g.resid,          g.C,     g.M,     g.N,
+              g.K,      g.qscale, g.qcols,         g.acc_scale,      g.out_inv_scale, group_m, nt_store};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
-  hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles), dim3(WGM * WGN * 64),
-                     0, s, p);
+  if constexpr (ST == 0) {
+    hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles),
+                       dim3(WGM * WGN * 64), 0, s, p);
+  } else {
+    static_assert(sizeof(TI) <= 2, "the LDS ring kernel serves BF16 and FP8 operands");
+    hipLaunchKernelGGL((gemm_dma_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, ST, OCC>), dim3(tiles),
+                       dim3(WGM * WGN * 64), 0, s, p);
+  }
 }
 
-#define ANON_CFG_CASE(i, bm, bn, bk, wgm, wgn, occ, name) \
-  case i:                                                  \
-    run<TI, TO, TR, EPI, bm, bn, bk, wgm, wgn, occ>(g, s); \
+#define ANON_CFG_CASE(i, bm, bn, bk, wgm, wgn, st, occ, name) \
+  case i:                                                      \
+    run<TI, TO, TR, EPI, bm, bn, bk, wgm, wgn, st, occ>(g, s); \
     return true;
 
 template <typename TI, typename TO, typename TR, int EPI>
@@ -410,7 +658,7 @@ int default_gemm_config(const GemmParams& g) {
   // the preferred tile of the type if it divides the shape, else the first
   // one that does
   const int n = gemm_num_configs(g.in);
-  const int pref = g.in == ET_BF16 ? 5 : (g.in == ET_FP8 ? 3 : 0);
+  const int pref = g.in == ET_BF16 ? 8 : (g.in == ET_FP8 ? 2 : 0);
   if (gemm_config_fits(g.in, pref, g.N, g.K)) return pref;
   for (int c = 0; c < n; ++c)
     if (gemm_config_fits(g.in, c, g.N, g.K)) return c;

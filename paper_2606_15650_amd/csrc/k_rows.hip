@@ -7,6 +7,8 @@
 // statistics are FP32 and two-pass (mean, then mean of squared deviations)
 // with a fixed butterfly reduction order, so a row's result never depends on
 // the other rows of the batch.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace anon {
@@ -252,6 +254,25 @@ __global__ void fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Values uniform in [-1, 1) from a 32-bit integer hash of the element index
+// (the "lowbias32" mixer of Chris Wellons' hash-prospector): operands with
+// the bit statistics of real activations, so that timed kernels draw the
+// power (and run at the clock) they do on real data.
+__global__ void fill_random_kernel(void* p, ElemType t, int64_t n, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t x = (uint32_t)i ^ (uint32_t)(i >> 32) * 0x9e3779b9u ^ seed;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    const float v = (float)(x >> 8) * (1.0f / 8388608.0f) - 1.0f;
+    if (t == ET_F32) ((float*)p)[i] = v;
+    else if (t == ET_BF16) ((bf16_t*)p)[i] = static_cast<bf16_t>(v);
+    else ((fp8_t*)p)[i].v = f32_to_e4m3(v);
+  }
+}
+
 #define ANON_NPL_SWITCH(NPLV, ...)            \
   switch (NPLV) {                             \
     case 1: { constexpr int NPL = 1; __VA_ARGS__; } break;   \
@@ -336,6 +357,12 @@ void launch_window_merge(const int* cu_seqlens, int B, const int* rec_win0, cons
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_u8_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_random(void* p, ElemType t, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 65536);
+  hipLaunchKernelGGL(fill_random_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, t, n, seed);
 }
 
 }  // namespace anon

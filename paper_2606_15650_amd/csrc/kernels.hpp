@@ -99,6 +99,8 @@ void launch_ps_write(const PcacheDev& pc, const uint8_t* text, const int64_t* cu
                      const int* sp_plen, const int64_t* sp_in_end, const uint8_t* digests, const int64_t* cu_out,
                      uint8_t* out, int64_t out_cap, uint32_t* err, hipStream_t s);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+// n elements of type t, uniform in [-1, 1) (benchmark and tuning operands)
+void launch_fill_random(void* p, ElemType t, int64_t n, uint32_t seed, hipStream_t s);
 
 // Shape of a created model (the struct itself is private to the runtime).
 const anon_model_config* model_config(const anon_model* m);

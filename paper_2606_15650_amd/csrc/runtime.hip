@@ -563,6 +563,10 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
       g.A = w.ffn, g.W = L.w2, g.bias = L.b2, g.resid = w.x2, g.res = m->act_t, g.C = w.y, g.N = h, g.K = f;
       g.epi = EPI_RESID, g.out = m->act_t;
     }
+    // random operands: zeros would time the tiles at a lower power draw
+    // (and higher clock) than real activations allow
+    launch_fill_random(const_cast<void*>(g.A), g.in, (int64_t)T * g.K, 0x1234u + gi, s);
+    if (g.epi == EPI_RESID) launch_fill_random(const_cast<void*>(g.resid), g.res, (int64_t)T * g.N, 0x5678u + gi, s);
     // two rounds over all configurations (5 timed launches each), keeping
     // each configuration's best mean; near-ties go to the default tile
     std::vector<float> best_ms(ncfg, 1e30f);

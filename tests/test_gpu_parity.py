@@ -389,11 +389,16 @@ def test_base_fp32_small_batch_vs_pure_oracle(torch_dev):
     m.close()
 
 
-def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch):
-    """Every GEMM tile shape gives the same bits (fixed K order): tuning never changes results."""
-    W, m = make_model(TINY, "bf16", 0)
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch, precision):
+    """Every GEMM tile shape (register-staged or LDS-ring kernel) gives the same
+    bits (fixed K order): tuning never changes results."""
+    scales = None
+    if precision == "fp8":
+        scales = np.asarray(_fp8_scales("tiny_fp8"), np.float32).reshape(-1)
+    W, m = make_model(TINY, precision, 0, act_scales=scales)
     names = m.tile_configs()
-    say(f"[tiles] {len(names)} bf16 tile configurations")
+    say(f"[tiles] {len(names)} {precision} tile configurations")
     ref = None
     h, f = TINY.hidden, TINY.ffn
     from paper_2606_15650_amd import api
@@ -411,6 +416,7 @@ def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch):
 
 
 def _fits(name, N, K):
+    # names: <type>_<BM>x<BN>x<BK>_w<WGM>x<WGN>[_s<stages>]
     bm, bn, bk = [int(x) for x in name.split("_")[1].split("x")]
     return N % bn == 0 and K % bk == 0
 

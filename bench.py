@@ -342,7 +342,8 @@ def main() -> int:
         db = DeviceBatch(rb)
         stream = torch.cuda.current_stream()
         tiles, _ = pl.autotune(T, B)
-        tiles = [model.tile_configs()[t] for t in tiles]
+        groups = model.get_tiles()[1]
+        tiles = [f"{model.tile_configs()[t]}_g{g}" for t, g in zip(tiles, groups)]
         for _ in range(warmup):
             pl.step(db)
         torch.cuda.synchronize()

@@ -134,7 +134,8 @@ anon_status ner_forward(anon_model* model, const int32_t* d_ids, const int32_t* 
  * using d_workspace (>= anon_ner_workspace_size(T, 1) bytes; overwritten) as
  * operand memory, and keeps the fastest for this model's later calls.  All
  * configurations of a precision form every output element with the same
- * MFMA sequence in the same K order, so tuning never changes results.
+ * MFMA sequence in the same K order, so tuning never changes results.  It
+ * then picks each GEMM's tile group (see anon_model_set_tile_groups).
  *   chosen:   [4] picked configuration per GEMM, or NULL
  *   times_ms: [4 * max_configs] mean time per configuration (-1: does not
  *             fit the shape), or NULL
@@ -143,6 +144,14 @@ anon_status anon_autotune(anon_model* model, int32_t T, void* d_workspace, size_
                           int32_t* chosen, float* times_ms, int32_t max_configs);
 /* Set the tile configuration of each encoder GEMM (-1 = built-in default). */
 anon_status anon_model_set_tiles(anon_model* model, const int32_t tiles[4]);
+/* Set the tile order of each encoder GEMM: output tiles are visited in
+ * groups of groups[i] row blocks, column block by column block (1 = plain
+ * row-major order).  Only the order in which workgroups take tiles changes
+ * (L2 reuse of the weight panels), never a result.  Range [1, 1024]. */
+anon_status anon_model_set_tile_groups(anon_model* model, const int32_t groups[4]);
+/* Current tile configuration and tile group of each encoder GEMM (either
+ * pointer may be NULL). */
+anon_status anon_model_get_tiles(const anon_model* model, int32_t tiles[4], int32_t groups[4]);
 /* Number of tile configurations of a precision and the name of one. */
 int32_t anon_tile_config_count(anon_precision precision);
 const char* anon_tile_config_name(anon_precision precision, int32_t config);

@@ -89,6 +89,8 @@ _SIGS = {
     "anon_server_stop": ([vp], i32),
     "anon_autotune": ([vp, i32, vp, sz, vp, C.POINTER(i32), C.POINTER(C.c_float), i32], i32),
     "anon_model_set_tiles": ([vp, C.POINTER(i32)], i32),
+    "anon_model_set_tile_groups": ([vp, C.POINTER(i32)], i32),
+    "anon_model_get_tiles": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
     "anon_tile_config_count": ([i32], i32),
     "anon_tile_config_name": ([i32, i32], C.c_char_p),
     "anon_prof_enable": ([i32, i32], i32),
@@ -185,6 +187,16 @@ class Model:
     def set_tiles(self, tiles):
         t = (i32 * 4)(*[int(x) for x in tiles])
         _check("anon_model_set_tiles", lib().anon_model_set_tiles(self.handle, t))
+
+    def set_tile_groups(self, groups):
+        g = (i32 * 4)(*[int(x) for x in groups])
+        _check("anon_model_set_tile_groups", lib().anon_model_set_tile_groups(self.handle, g))
+
+    def get_tiles(self) -> tuple[list[int], list[int]]:
+        """(tile configuration, tile group) of each encoder GEMM."""
+        t, g = (i32 * 4)(), (i32 * 4)()
+        _check("anon_model_get_tiles", lib().anon_model_get_tiles(self.handle, t, g))
+        return list(t), list(g)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -21,7 +21,6 @@
 // Epilogues: bias (+ exact scaling of the Q columns by 1/sqrt(d)); bias + GELU;
 // bias + residual added in FP32 and rounded once to the output type.
 #include <algorithm>
-#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -114,7 +113,6 @@ struct DevParams {
   float acc_scale;
   float out_inv_scale;
   int group_m;
-  int nt_store;
 };
 
 // Epilogue staging: once the K loop is done, the operand LDS is reused and
@@ -202,17 +200,13 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
           if constexpr (sizeof(TO) == 2) {
             const bf16x4 o = bf16x4{static_cast<bf16_t>(s4[0] + rv[0]), static_cast<bf16_t>(s4[1] + rv[1]),
                                     static_cast<bf16_t>(s4[2] + rv[2]), static_cast<bf16_t>(s4[3] + rv[3])};
-            if (p.nt_store) __builtin_nontemporal_store(o, (bf16x4*)dst);
-            else *(bf16x4*)dst = o;
+            *(bf16x4*)dst = o;
           } else {
             const floatx4 o = floatx4{s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
-            if (p.nt_store) __builtin_nontemporal_store(o, (floatx4*)dst);
-            else *(floatx4*)dst = o;
+            *(floatx4*)dst = o;
           }
         } else {
-          const intx4 o = *(const intx4*)src;
-          if (p.nt_store) __builtin_nontemporal_store(o, (intx4*)(C + (size_t)grow * N + gcol));
-          else *(intx4*)(C + (size_t)grow * N + gcol) = o;
+          *(intx4*)(C + (size_t)grow * N + gcol) = *(const intx4*)src;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -361,6 +355,34 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
+// Instruction order of one k-step (a scheduling region): the next k-step's
+// fragment reads go out two per MFMA from the first MFMA on, so their
+// latency hides behind the rest of the step's MFMA chain; then the ring
+// refill loads (last k-step of a tile), two per MFMA; then the other MFMAs.
+template <int NMF, int NRD, int NVM>
+__device__ __forceinline__ void sched_step() {
+  constexpr int RG = (NRD + 1) / 2, VG = (NVM + 1) / 2;
+#pragma unroll
+  for (int r = 0; r < NRD / 2; ++r) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // DS read
+  }
+  if constexpr (NRD % 2) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < NVM / 2; ++v) {
+    if (RG + v < NMF) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x010, 2, 0);  // VMEM
+  }
+  if constexpr (NVM % 2) {
+    if (RG + VG - 1 < NMF) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+  }
+  if constexpr (NMF > RG + VG) __builtin_amdgcn_sched_group_barrier(0x008, NMF - RG - VG, 0);
+}
+
 template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST,
           int OCC>
 __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams p) {
@@ -491,7 +513,10 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
         for (int j = 0; j < TN; ++j) fb[cur ^ 1][j] = rdfrag(base, boff[ks + 1 < NKS ? ks + 1 : 0], j);
       } else {
         // this wave's reads of the tile have returned before anyone may
-        // overwrite it; tile kt+1 has landed for this wave
+        // overwrite it; tile kt+1 has landed for this wave.  (No instruction
+        // crosses this point: the previous k-step's MFMAs stay ahead of the
+        // wait, covering the latency of the reads it waits for.)
+        __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) (vmcnt, expcnt at maxima)
         wait_vmcnt<(ST - 2) * LPT>();
         __builtin_amdgcn_s_barrier();
@@ -506,6 +531,11 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[cur][i], fb[cur][j], acc[i][j]);
+      // (with two workgroups per CU the hardware interleaves them better)
+      if constexpr (OCC == 1) {
+        if (ks + 1 < NKS) sched_step<TM * TN, (TM + TN) * NCH, 0>();
+        else sched_step<TM * TN, (TM + TN) * NCH, LPT>();
+      }
     }
     stage = nstage;
   };
@@ -519,11 +549,6 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
   // and every wave must have finished reading it
   __syncthreads();
   epilogue<TO, TR, EPI, TM, TN, NW, SMEM>(p, acc, smem, wave, lane, m0 + wm * WTM, n0 + wn * WTN);
-}
-
-int env_int(const char* name, int def) {
-  const char* v = getenv(name);
-  return v && *v ? atoi(v) : def;
 }
 
 struct Cfg {
@@ -580,10 +605,8 @@ const Cfg* cfgs(ElemType t, int* n) {
 
 template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST, int OCC>
 void run(const GemmParams& g, hipStream_t s) {
-  static const int group_m = std::max(1, env_int("ANON_GEMM_GROUP_M", 1));
-  static const int nt_store = env_int("ANON_GEMM_NT", 0);
-  DevParams p{g.A,      g.W,      g.bias,          g.resid,          g.C,     g.M,     g.N,
-              g.K,      g.qscale, g.qcols,         g.acc_scale,      g.out_inv_scale, group_m, nt_store};
+  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale,
+              std::max(1, g.group_m)};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
   if constexpr (ST == 0) {
     hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles),

@@ -23,6 +23,7 @@ struct GemmParams {
   ElemType in, out, res;
   GemmEpi epi;
   int config;         // tile configuration index (-1: default choice)
+  int group_m;        // row blocks per tile group (<= 1: row-major tile order)
 };
 // Returns false (and sets the error) if no kernel matches the shapes/types.
 bool launch_gemm(const GemmParams& p, hipStream_t s);

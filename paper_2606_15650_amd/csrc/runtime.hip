@@ -111,6 +111,7 @@ struct anon_model {
   ElemType act_t;   // stored hidden state / residual
   ElemType qkv_t;   // Q, K, V and attention operands
   int gemm_cfg[4] = {-1, -1, -1, -1};
+  int gemm_gm[4] = {1, 1, 1, 1};  // row blocks per tile group
 };
 
 const anon_model_config* anon::model_config(const anon_model* m) { return &m->cfg; }
@@ -385,6 +386,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.qcols = h;
     g.acc_scale = fp8 ? L.sa[0] * L.sw[0] : 1.f;
     g.config = m->gemm_cfg[0];
+    g.group_m = m->gemm_gm[0];
     {
       ProfScope ps(KC_QKV, s, gemm_flops(T, 3 * h, h));
       if (!launch_gemm(g, s)) return ANON_EINVAL;
@@ -409,6 +411,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.qcols = 0;
     g.acc_scale = fp8 ? L.sa[1] * L.sw[1] : 1.f;
     g.config = m->gemm_cfg[1];
+    g.group_m = m->gemm_gm[1];
     {
       ProfScope ps(KC_OPROJ, s, gemm_flops(T, h, h));
       if (!launch_gemm(g, s)) return ANON_EINVAL;
@@ -430,6 +433,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.acc_scale = fp8 ? L.sa[2] * L.sw[2] : 1.f;
     g.out_inv_scale = fp8 ? 1.f / L.sa[3] : 1.f;
     g.config = m->gemm_cfg[2];
+    g.group_m = m->gemm_gm[2];
     {
       ProfScope ps(KC_FFN1, s, gemm_flops(T, f, h));
       if (!launch_gemm(g, s)) return ANON_EINVAL;
@@ -448,6 +452,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     g.acc_scale = fp8 ? L.sa[3] * L.sw[3] : 1.f;
     g.out_inv_scale = 1.f;
     g.config = m->gemm_cfg[3];
+    g.group_m = m->gemm_gm[3];
     {
       ProfScope ps(KC_FFN2, s, gemm_flops(T, h, f));
       if (!launch_gemm(g, s)) return ANON_EINVAL;
@@ -520,6 +525,23 @@ anon_status anon_model_set_tiles(anon_model* m, const int32_t tiles[4]) {
     if (tiles[i] >= 0 && !gemm_config_fits(m->gemm_t, tiles[i], NK[i][0], NK[i][1]))
       return set_error(ANON_EINVAL, "tile configuration does not fit GEMM " + std::to_string(i));
   for (int i = 0; i < 4; ++i) m->gemm_cfg[i] = tiles[i];
+  return ANON_OK;
+}
+
+anon_status anon_model_set_tile_groups(anon_model* m, const int32_t groups[4]) {
+  if (!m || !groups) return set_error(ANON_EINVAL, "NULL argument");
+  for (int i = 0; i < 4; ++i)
+    if (groups[i] < 1 || groups[i] > 1024) return set_error(ANON_EINVAL, "tile group must be in [1, 1024]");
+  for (int i = 0; i < 4; ++i) m->gemm_gm[i] = groups[i];
+  return ANON_OK;
+}
+
+anon_status anon_model_get_tiles(const anon_model* m, int32_t tiles[4], int32_t groups[4]) {
+  if (!m) return set_error(ANON_EINVAL, "NULL argument");
+  for (int i = 0; i < 4; ++i) {
+    if (tiles) tiles[i] = m->gemm_cfg[i];
+    if (groups) groups[i] = m->gemm_gm[i];
+  }
   return ANON_OK;
 }
 
@@ -604,6 +626,34 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
     }
     m->gemm_cfg[gi] = best_c;
     if (chosen) chosen[gi] = best_c;
+    // then the tile order of the chosen shape: groups of row blocks walked
+    // column by column keep the weight panels in L2 when W exceeds it
+    g.config = best_c;
+    int best_g = 1;
+    float best_g_ms = best_ms[best_c];
+    for (int gm : {4, 8, 16}) {
+      g.group_m = gm;
+      float t = 1e30f;
+      for (int round = 0; round < 2 && st == ANON_OK; ++round) {
+        launch_gemm(g, s);
+        const int reps = 5;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) launch_gemm(g, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          st = set_error(ANON_EDEVICE, "autotune: kernel failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t = std::min(t, ms / reps);
+      }
+      if (t < best_g_ms * 0.98f) {
+        best_g_ms = t;
+        best_g = gm;
+      }
+    }
+    m->gemm_gm[gi] = best_g;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

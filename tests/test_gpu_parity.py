@@ -413,6 +413,15 @@ def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch, precision)
             ref = z
         else:
             np.testing.assert_array_equal(z, ref, err_msg=names[ci])
+    # the tile order (groups of row blocks) changes no result either
+    m.set_tiles([-1] * 4)
+    for groups in ([2, 3, 4, 8], [16, 16, 16, 16]):
+        m.set_tile_groups(groups)
+        lab, z, _ = _run_ner(m, tiny_batch)
+        np.testing.assert_array_equal(z, ref, err_msg=str(groups))
+        assert m.get_tiles()[1] == groups
+    with pytest.raises(RuntimeError):
+        m.set_tile_groups([0, 1, 1, 1])
 
 
 def _fits(name, N, K):

@@ -31,6 +31,32 @@ PEAK_FLOPS = {"bf16": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12}
 PEAK_HBM = 8.0e12
 
 
+# kernel class -> source file whose kernels it launches
+KERNEL_SOURCE = {"qkv": "k_gemm.hip", "oproj": "k_gemm.hip", "ffn1": "k_gemm.hip", "ffn2": "k_gemm.hip",
+                 "attn": "k_attn.hip"}
+
+
+def counter_traffic(workload: str, kernel: str, tile: str | None):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by the reading of a
+    1 GiB copy), or None when there is none, it was taken on another tile, or
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_{kernel}_counters.json")
+    src = KERNEL_SOURCE.get(kernel)
+    if not src or not os.path.exists(path):
+        return None, "no counter summary"
+    with open(path) as f:
+        c = json.load(f)
+    with open(os.path.join(ROOT, "paper_2606_15650_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if c.get("source_sha256") != sha:
+        return None, f"{src} changed since the counters were taken"
+    if tile is not None and c.get("tile") != tile:
+        return None, f"counters taken on tile {c.get('tile')}, this run chose {tile}"
+    return float(c["bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def attention_flops(cu: np.ndarray, cfg) -> float:
     """Algorithmic attention FLOPs of one layer: QK^T and PV over each record."""
     L = np.diff(cu).astype(np.float64)
@@ -343,7 +369,7 @@ def main() -> int:
         stream = torch.cuda.current_stream()
         tiles, _ = pl.autotune(T, B)
         groups = model.get_tiles()[1]
-        tiles = [f"{model.tile_configs()[t]}_g{g}" for t, g in zip(tiles, groups)]
+        tiles = [f"{model.tile_configs()[t]}_g{g if g else 'auto'}" for t, g in zip(tiles, groups)]
         for _ in range(warmup):
             pl.step(db)
         torch.cuda.synchronize()
@@ -389,9 +415,11 @@ def main() -> int:
         flops_per_launch = None
     avg_ms = d["ms"] / max(d["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) if flops_per_launch else None
+    tile_of = dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles))
+    traffic, traffic_src = counter_traffic(wl.name, dom, tile_of.get(dom))
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms,
-                "flops_per_launch": flops_per_launch}
+                "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
+                "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch}
     breakdown = {}
     for k, v in kern.items():
         if v["launches"]:

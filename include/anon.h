@@ -134,8 +134,7 @@ anon_status ner_forward(anon_model* model, const int32_t* d_ids, const int32_t* 
  * using d_workspace (>= anon_ner_workspace_size(T, 1) bytes; overwritten) as
  * operand memory, and keeps the fastest for this model's later calls.  All
  * configurations of a precision form every output element with the same
- * MFMA sequence in the same K order, so tuning never changes results.  It
- * then picks each GEMM's tile group (see anon_model_set_tile_groups).
+ * MFMA sequence in the same K order, so tuning never changes results.
  *   chosen:   [4] picked configuration per GEMM, or NULL
  *   times_ms: [4 * max_configs] mean time per configuration (-1: does not
  *             fit the shape), or NULL
@@ -146,8 +145,10 @@ anon_status anon_autotune(anon_model* model, int32_t T, void* d_workspace, size_
 anon_status anon_model_set_tiles(anon_model* model, const int32_t tiles[4]);
 /* Set the tile order of each encoder GEMM: output tiles are visited in
  * groups of groups[i] row blocks, column block by column block (1 = plain
- * row-major order).  Only the order in which workgroups take tiles changes
- * (L2 reuse of the weight panels), never a result.  Range [1, 1024]. */
+ * row-major order; 0 = by shape, the default: 8 when a row block spans 8 or
+ * more column blocks, else 1).  Only the order in which workgroups take
+ * tiles changes (L2 reuse of the weight panels), never a result.  Range
+ * [0, 1024]. */
 anon_status anon_model_set_tile_groups(anon_model* model, const int32_t groups[4]);
 /* Current tile configuration and tile group of each encoder GEMM (either
  * pointer may be NULL). */

@@ -605,8 +605,11 @@ const Cfg* cfgs(ElemType t, int* n) {
 
 template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST, int OCC>
 void run(const GemmParams& g, hipStream_t s) {
-  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale,
-              std::max(1, g.group_m)};
+  // tile order: by default, groups of 8 row blocks when a row block spans 8
+  // or more column blocks (its weight panels would otherwise cycle through
+  // the XCD's L2 once per row block), else plain row-major order
+  const int gm = g.group_m > 0 ? g.group_m : (g.N / BN >= 8 ? 8 : 1);
+  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale, gm};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
   if constexpr (ST == 0) {
     hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles),

@@ -23,7 +23,7 @@ struct GemmParams {
   ElemType in, out, res;
   GemmEpi epi;
   int config;         // tile configuration index (-1: default choice)
-  int group_m;        // row blocks per tile group (<= 1: row-major tile order)
+  int group_m;        // row blocks per tile group (0: chosen by shape; 1: row-major)
 };
 // Returns false (and sets the error) if no kernel matches the shapes/types.
 bool launch_gemm(const GemmParams& p, hipStream_t s);

@@ -111,7 +111,7 @@ struct anon_model {
   ElemType act_t;   // stored hidden state / residual
   ElemType qkv_t;   // Q, K, V and attention operands
   int gemm_cfg[4] = {-1, -1, -1, -1};
-  int gemm_gm[4] = {1, 1, 1, 1};  // row blocks per tile group
+  int gemm_gm[4] = {0, 0, 0, 0};  // row blocks per tile group (0: by shape)
 };
 
 const anon_model_config* anon::model_config(const anon_model* m) { return &m->cfg; }
@@ -531,7 +531,7 @@ anon_status anon_model_set_tiles(anon_model* m, const int32_t tiles[4]) {
 anon_status anon_model_set_tile_groups(anon_model* m, const int32_t groups[4]) {
   if (!m || !groups) return set_error(ANON_EINVAL, "NULL argument");
   for (int i = 0; i < 4; ++i)
-    if (groups[i] < 1 || groups[i] > 1024) return set_error(ANON_EINVAL, "tile group must be in [1, 1024]");
+    if (groups[i] < 0 || groups[i] > 1024) return set_error(ANON_EINVAL, "tile group must be in [0, 1024]");
   for (int i = 0; i < 4; ++i) m->gemm_gm[i] = groups[i];
   return ANON_OK;
 }
@@ -626,34 +626,6 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
     }
     m->gemm_cfg[gi] = best_c;
     if (chosen) chosen[gi] = best_c;
-    // then the tile order of the chosen shape: groups of row blocks walked
-    // column by column keep the weight panels in L2 when W exceeds it
-    g.config = best_c;
-    int best_g = 1;
-    float best_g_ms = best_ms[best_c];
-    for (int gm : {4, 8, 16}) {
-      g.group_m = gm;
-      float t = 1e30f;
-      for (int round = 0; round < 2 && st == ANON_OK; ++round) {
-        launch_gemm(g, s);
-        const int reps = 5;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps; ++r) launch_gemm(g, s);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-          st = set_error(ANON_EDEVICE, "autotune: kernel failed");
-          break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        t = std::min(t, ms / reps);
-      }
-      if (t < best_g_ms * 0.98f) {
-        best_g_ms = t;
-        best_g = gm;
-      }
-    }
-    m->gemm_gm[gi] = best_g;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

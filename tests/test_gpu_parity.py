@@ -421,7 +421,7 @@ def test_tile_configurations_are_bit_identical(torch_dev, tiny_batch, precision)
         np.testing.assert_array_equal(z, ref, err_msg=str(groups))
         assert m.get_tiles()[1] == groups
     with pytest.raises(RuntimeError):
-        m.set_tile_groups([0, 1, 1, 1])
+        m.set_tile_groups([-1, 1, 1, 1])
 
 
 def _fits(name, N, K):

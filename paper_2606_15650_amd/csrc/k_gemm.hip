@@ -70,13 +70,15 @@ __device__ __forceinline__ void st(fp8_t* p, float v) { p->v = f32_to_e4m3(v); }
 // of the instructions of a full-precision erff in an epilogue that runs
 // once per output element.
 __device__ __forceinline__ float gelu_erf(float v) {
-  const float x = v * 0.70710678118654752f;
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
-  const float poly = ((((1.061405429f * t - 1.453152027f) * t + 1.421413741f) * t - 0.284496736f) * t +
-                      0.254829592f) * t;
-  const float e = 1.0f - poly * __expf(-ax * ax);
-  return 0.5f * v * (1.0f + copysignf(e, x));
+  // Phi(v) = 1 - q for v >= 0 and q for v < 0, with q = P(t) exp(-v^2/2) / 2,
+  // t = 1 / (1 + p |v| / sqrt 2); the 1/2 and 1/sqrt 2 are folded into the
+  // constants, and exp(-v^2/2) = exp2(-(v sqrt(log2(e)/2))^2)
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(v), 1.0f));
+  const float P = ((((0.5f * 1.061405429f * t - 0.5f * 1.453152027f) * t + 0.5f * 1.421413741f) * t -
+                    0.5f * 0.284496736f) * t + 0.5f * 0.254829592f) * t;
+  const float sv = v * 0.84932180028801904f;
+  const float r = v * (P * __builtin_amdgcn_exp2f(-(sv * sv)));
+  return v >= 0.0f ? v - r : r;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -115,71 +117,88 @@ struct DevParams {
   int group_m;
 };
 
-// Epilogue staging: once the K loop is done, the operand LDS is reused and
-// each wave parks SR rows of its tile in row-major order, then writes them
-// back with 16-byte row-contiguous accesses.  TS is the staged type: FP32 for
-// the residual epilogue (the residual is added before rounding), else TO.
-template <typename TO, int EPI, int BN_W, int NW, int SMEM>
+// The MFMAs take the weight fragment as their first operand, so each
+// accumulator holds a 32x32 block of C^T: lane l, register r holds row
+// (l & 31) and column (r/4)*8 + (l/32)*4 + r%4 of the block -- four
+// consecutive columns of one row per register quad.
+//
+// Epilogue staging: once the K loop is done, the operand LDS is reused; each
+// wave parks a 32-row strip of JP column blocks in row-major order (one 8- or
+// 16-byte write per register quad), then writes it back with 16-byte
+// row-contiguous accesses.  TS is the staged type: FP32 for the residual
+// epilogue (the residual is added before rounding), else TO.
+template <typename TO, int EPI, int TN, int NW, int SMEM>
 struct Staging {
   typedef typename std::conditional<EPI == EPI_RESID, float, TO>::type TS;
   static constexpr int SPAD = 16 / (int)sizeof(TS);
-  static constexpr int SROW = BN_W + SPAD;
-  static constexpr int SR = (NW * 32 * SROW * (int)sizeof(TS) <= SMEM) ? 32 : 16;
-  static_assert(NW * SR * SROW * (int)sizeof(TS) <= SMEM, "epilogue staging does not fit");
+  static constexpr int bytes(int jp) { return NW * 32 * (jp * 32 + SPAD) * (int)sizeof(TS); }
+  static constexpr int JP = bytes(TN) <= SMEM ? TN : (bytes(TN / 2) <= SMEM ? TN / 2 : 1);
+  static constexpr int SROW = JP * 32 + SPAD;
+  static_assert(bytes(JP) <= SMEM && TN % JP == 0, "epilogue staging does not fit");
 };
 
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) { *(floatx4*)p = floatx4{v[0], v[1], v[2], v[3]}; }
+__device__ __forceinline__ void st4(bf16_t* p, const float (&v)[4]) {
+  *(bf16x4*)p = bf16x4{static_cast<bf16_t>(v[0]), static_cast<bf16_t>(v[1]), static_cast<bf16_t>(v[2]),
+                       static_cast<bf16_t>(v[3])};
+}
+__device__ __forceinline__ void st4(fp8_t* p, const float (&v)[4]) {
+  float c[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c[e] = fminf(fmaxf(v[e], -448.0f), 448.0f);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], w, true);
+  *(int*)p = w;
+}
+
 // Applies the epilogue to a wave's (TM*32) x (TN*32) accumulator block whose
-// top-left output element is (wrow0, wcol0).  Lane owns column (lane & 31) of
-// each 32x32 tile and rows (r/4)*8 + (lane/32)*4 + r%4 of register r.
+// top-left output element is (wrow0, wcol0).
 template <typename TO, typename TR, int EPI, int TM, int TN, int NW, int SMEM>
 __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM][TN], char* smem, int wave, int lane,
                                          int wrow0, int wcol0) {
-  constexpr int WTN = TN * 32;
-  typedef Staging<TO, EPI, WTN, NW, SMEM> SG;
+  typedef Staging<TO, EPI, TN, NW, SMEM> SG;
   typedef typename SG::TS TS;
-  constexpr int SR = SG::SR, SROW = SG::SROW;
+  constexpr int JP = SG::JP, SROW = SG::SROW;
   const int M = p.M, N = p.N;
   TO* __restrict__ C = (TO*)p.C;
-  TS* stg = reinterpret_cast<TS*>(smem) + wave * SR * SROW;
-  float bias[TN], qs[TN];
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int col = wcol0 + j * 32 + (lane & 31);
-    bias[j] = p.bias[col];
-    qs[j] = (EPI == EPI_BIAS && col < p.qcols) ? p.qscale : 1.0f;
-  }
+  TS* stg = reinterpret_cast<TS*>(smem) + wave * 32 * SROW;
   constexpr int CH = 16 / (int)sizeof(TS);  // staged elements per 16-byte chunk
-  constexpr int CPRS = WTN / CH;            // chunks per staged row
+  constexpr int CPRS = JP * 32 / CH;        // chunks per staged row
+  const int lrow = lane & 31, lq = (lane >> 5) * 4;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
 #pragma unroll
-    for (int pass = 0; pass < 32 / SR; ++pass) {
-      // 1. stage rows [pass*SR, pass*SR + SR) of sub-tile i, row-major;
-      //    accumulator registers r hold rows (r/4)*8 + (lane/32)*4 + r%4, so
-      //    SR rows are the registers [pass*SR/2, (pass+1)*SR/2)
+    for (int j0 = 0; j0 < TN; j0 += JP) {
+      // 1. stage columns [j0*32, (j0+JP)*32) of the strip's 32 rows
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
+      for (int jj = 0; jj < JP; ++jj) {
 #pragma unroll
-        for (int r = pass * (SR / 2); r < (pass + 1) * (SR / 2); ++r) {
-          const int rin = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3) - pass * SR;
-          float v = acc[i][j][r] * p.acc_scale + bias[j];
-          if (EPI == EPI_BIAS) {
-            v *= qs[j];
-          } else if (EPI == EPI_GELU) {
-            v = gelu_erf(v);
-            // FP8 output: the activation is a bf16 value first (as in the
-            // BF16 path), then scaled and rounded to E4M3
-            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * p.out_inv_scale;
+        for (int q = 0; q < 4; ++q) {
+          const int col = wcol0 + (j0 + jj) * 32 + q * 8 + lq;
+          const floatx4 b4 = *(const floatx4*)(p.bias + col);
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float x = acc[i][j0 + jj][q * 4 + e] * p.acc_scale + b4[e];
+            if (EPI == EPI_BIAS) {
+              if (col + e < p.qcols) x *= p.qscale;
+            } else if (EPI == EPI_GELU) {
+              x = gelu_erf(x);
+              // FP8 output: the activation is a bf16 value first (as in the
+              // BF16 path), then scaled and rounded to E4M3
+              if (sizeof(TO) == 1) x = static_cast<float>(static_cast<bf16_t>(x)) * p.out_inv_scale;
+            }
+            v[e] = x;
           }
-          st(stg + rin * SROW + j * 32 + (lane & 31), v);
+          st4(stg + lrow * SROW + jj * 32 + q * 8 + lq, v);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       // 2. write the rows back with 16-byte (staged) chunks
-      for (int c = lane; c < SR * CPRS; c += 64) {
+      for (int c = lane; c < 32 * CPRS; c += 64) {
         const int rr = c / CPRS, cc = c % CPRS;
-        const int grow = wrow0 + i * 32 + pass * SR + rr, gcol = wcol0 + cc * CH;
+        const int grow = wrow0 + i * 32 + rr, gcol = wcol0 + j0 * 32 + cc * CH;
         if (grow >= M) continue;
         const TS* src = stg + rr * SROW + cc * CH;
         if constexpr (EPI == EPI_RESID) {
@@ -196,15 +215,8 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
 #pragma unroll
             for (int k = 0; k < 4; ++k) rv[k] = r4[k];
           }
-          TO* dst = C + (size_t)grow * N + gcol;
-          if constexpr (sizeof(TO) == 2) {
-            const bf16x4 o = bf16x4{static_cast<bf16_t>(s4[0] + rv[0]), static_cast<bf16_t>(s4[1] + rv[1]),
-                                    static_cast<bf16_t>(s4[2] + rv[2]), static_cast<bf16_t>(s4[3] + rv[3])};
-            *(bf16x4*)dst = o;
-          } else {
-            const floatx4 o = floatx4{s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
-            *(floatx4*)dst = o;
-          }
+          const float o[4] = {s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
+          st4(C + (size_t)grow * N + gcol, o);
         } else {
           *(intx4*)(C + (size_t)grow * N + gcol) = *(const intx4*)src;
         }
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(a[cur][i], b[cur][j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(b[cur][j], a[cur][i], acc[i][j]);
     }
     if (kt + 1 < KT) lstore(buf ^ 1);
     __syncthreads();
@@ -530,7 +542,7 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fa[cur][i], fb[cur][j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(fb[cur][j], fa[cur][i], acc[i][j]);
       // (with two workgroups per CU the hardware interleaves them better)
       if constexpr (OCC == 1) {
         if (ks + 1 < NKS) sched_step<TM * TN, (TM + TN) * NCH, 0>();

@@ -45,6 +45,11 @@ __device__ __forceinline__ void st(float* p, float v) { *p = v; }
 __device__ __forceinline__ void st(bf16_t* p, float v) { *p = static_cast<bf16_t>(v); }
 __device__ __forceinline__ void st(fp8_t* p, float v) { p->v = f32_to_e4m3(v); }
 
+// 2^x for x <= 0 with the bare v_exp_f32: results below 2^-126 may flush to
+// zero, a difference far below the bf16 rounding of p and invisible in the
+// FP32 row sums
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
 constexpr int D = 64;    // head dim
 constexpr int KT = 64;   // keys per LDS tile
 
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float pv = exp2f(s[kb][r] - m);
+          const float pv = exp2_fast(s[kb][r] - m);
           s[kb][r] = pv;
           ps += pv;
         }
@@ -231,7 +236,8 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // and V^T in LDS once; its waves then take 32-row query chunks in turn and
 // run both passes over the resident keys with no further barrier.  The V^T
 // row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
-// 32 lanes on distinct banks.
+// 32 lanes on distinct banks.  Records are binned by length so that RMAX and
+// the wave count follow the record (see kClassMax).
 // PAIR: two independent key blocks per iteration (more MFMA chains in flight
 // per wave, at the cost of registers).
 template <typename TO, int RMAX, int WAVES, bool PAIR>
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
       const float mb = mraw * LOG2E;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float p = exp2f(fmaf(s[r], LOG2E, -mb));
+        const float p = exp2_fast(fmaf(s[r], LOG2E, -mb));
         s[r] = p;
         lsum += p;
       }
@@ -386,15 +392,13 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
 
 constexpr int kWaves = 4;
 constexpr int kBQ = 32 * kWaves;
-constexpr int kShortMax = 128;   // records up to this length use the small resident kernel
+// Record-resident length classes: records of (kClassMax[c-1], kClassMax[c]]
+// keys go to a kernel whose LDS holds kClassMax[c] keys and whose waves
+// cover that many query rows (32 each), so shorter records fit more
+// workgroups per CU and leave fewer waves idle.
+constexpr int kClasses = 4;
+constexpr int kClassMax[kClasses] = {128, 256, 384, 512};
 constexpr int kResidentMax = 512;
-#ifndef ANON_ATTN_LONG_PAIR
-#define ANON_ATTN_LONG_PAIR 0
-#endif
-// long records: 16 waves (4 per SIMD) with one key block per iteration, or
-// 8 waves with two
-constexpr bool kLongPair = ANON_ATTN_LONG_PAIR != 0;
-constexpr int kLongWaves = kLongPair ? 8 : 16;
 
 // One workgroup: validates cu_seqlens and lists (record, q-block) items for
 // the records whose length lies in [lo, hi].
@@ -445,22 +449,39 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
 
 bool resident(ElemType t, int max_len) { return t == ET_BF16 && max_len <= kResidentMax; }
 
+template <typename TO>
+void launch_resident(const bf16_t* q, TO* out, const int4* items, int per_class, const int* counts, int n_heads,
+                     int hidden, float out_inv_scale, hipStream_t s) {
+  const dim3 grid(per_class, n_heads);
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 128, 4, false>), grid, dim3(4 * 64), 0, s, q, out, items, counts,
+                     hidden, out_inv_scale);
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 256, 8, false>), grid, dim3(8 * 64), 0, s, q, out,
+                     items + per_class, counts + 1, hidden, out_inv_scale);
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 384, 12, false>), grid, dim3(12 * 64), 0, s, q, out,
+                     items + 2 * per_class, counts + 2, hidden, out_inv_scale);
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 512, 16, false>), grid, dim3(16 * 64), 0, s, q, out,
+                     items + 3 * per_class, counts + 3, hidden, out_inv_scale);
+}
+
 }  // namespace
 
 int attn_plan_items(ElemType t, int max_len, int T, int B) {
-  // resident: one item per record in each of two length classes;
+  // resident: one item per record in each length class;
   // tiled: one item per 128-row q-block
-  return resident(t, max_len) ? 2 * (B + 1) : T / kBQ + B + 1;
+  return resident(t, max_len) ? kClasses * (B + 1) : T / kBQ + B + 1;
 }
+
+int attn_plan_counts() { return kClasses; }
 
 void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
                       int* counts, uint32_t* err, hipStream_t s) {
   if (resident(t, max_len)) {
-    const int half = max_items / 2;
-    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 1, kShortMax,
-                       1 << 30, items, half, counts, err);
-    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, kShortMax + 1,
-                       max_len, 1 << 30, items + half, half, counts + 1, err);
+    const int per = max_items / kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+      const int lo = c == 0 ? 1 : kClassMax[c - 1] + 1;
+      hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, lo, kClassMax[c],
+                         1 << 30, items + c * per, per, counts + c, err);
+    }
   } else {
     hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 0, max_len, kBQ,
                        items, max_items, counts, err);
@@ -472,21 +493,13 @@ void launch_attention(const void* qkv, void* out, const int4* items, int max_ite
                       hipStream_t s) {
   if (max_items <= 0) return;
   if (resident(t, max_len)) {
-    const int half = max_items / 2;
-    const bf16_t* q = (const bf16_t*)qkv;
-    if (out_t == ET_FP8) {
-      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kShortMax, 4, false>), dim3(half, n_heads), dim3(256), 0, s,
-                         q, (fp8_t*)out, items, counts, hidden, out_inv_scale);
-      hipLaunchKernelGGL((attn_resident_kernel<fp8_t, kResidentMax, kLongWaves, kLongPair>), dim3(half, n_heads),
-                         dim3(kLongWaves * 64), 0, s, q, (fp8_t*)out, items + half, counts + 1, hidden,
-                         out_inv_scale);
-    } else {
-      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kShortMax, 4, false>), dim3(half, n_heads), dim3(256), 0, s,
-                         q, (bf16_t*)out, items, counts, hidden, out_inv_scale);
-      hipLaunchKernelGGL((attn_resident_kernel<bf16_t, kResidentMax, kLongWaves, kLongPair>), dim3(half, n_heads),
-                         dim3(kLongWaves * 64), 0, s, q, (bf16_t*)out, items + half, counts + 1, hidden,
-                         out_inv_scale);
-    }
+    const int per = max_items / kClasses;
+    if (out_t == ET_FP8)
+      launch_resident(static_cast<const bf16_t*>(qkv), (fp8_t*)out, items, per, counts, n_heads, hidden,
+                      out_inv_scale, s);
+    else
+      launch_resident(static_cast<const bf16_t*>(qkv), (bf16_t*)out, items, per, counts, n_heads, hidden,
+                      out_inv_scale, s);
     return;
   }
   dim3 grid(max_items, n_heads);

@@ -35,8 +35,9 @@ bool gemm_config_fits(ElemType in, int config, int N, int K);
 // ---- attention ------------------------------------------------------------
 // Attention work list: validates cu_seqlens and lists the work items of the
 // kernel variant that serves (operand type, max record length).  `counts`
-// holds 2 ints.
+// holds attn_plan_counts() ints.
 int attn_plan_items(ElemType t, int max_len, int T, int B);
+int attn_plan_counts();  // ints the plan writes to `counts`
 void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
                       int* counts, uint32_t* err, hipStream_t s);
 void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* counts,

@@ -336,7 +336,7 @@ static void enc_layout(const anon_model* m, int T, int B, Carver& k, EncWs& w) {
   w.ffn = k.take<uint8_t>(T * f * g);
   w.max_q = attn_plan_items(m->qkv_t, m->cfg.max_pos, T, B);
   w.qblocks = k.take<int4>(w.max_q);
-  w.nq = k.take<int>(2);
+  w.nq = k.take<int>(attn_plan_counts());
 }
 
 static anon_status check_batch(const anon_model* m, const void* d_ids, const void* d_cu, int B, int T) {

@@ -430,31 +430,35 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
   group_tile(xcd_remap(blockIdx.x, ntm * ntn), ntm, ntn, p.group_m, mb, nb);
   const int m0 = mb * BM, n0 = nb * BN;
 
-  // this lane's source of each load instruction at k = 0 (rows past M, in
-  // the last row block only, re-read row M-1: never stored, no branch)
-  const TI* ga[A_INS];
-  const TI* gb[B_INS];
+  // this lane's source of each load instruction, as a byte offset from the
+  // tile's first row at k = 0 (uniform bases stay in scalar registers; rows
+  // past M, in the last row block only, re-read row M-1: never stored, no
+  // branch)
+  const char* const abase = (const char*)p.A + (size_t)m0 * K * sizeof(TI);
+  const char* const bbase = (const char*)p.W + (size_t)n0 * K * sizeof(TI);
+  uint32_t ga[A_INS], gb[B_INS];
   {
     const int rl = lane / CPR, slot = lane % CPR;
 #pragma unroll
     for (int i = 0; i < A_INS; ++i) {
       const int r = (wave * A_INS + i) * RPI + rl;
-      ga[i] = (const TI*)p.A + (size_t)min(m0 + r, M - 1) * K + (slot ^ lds_swz<CPR>(r)) * EPC;
+      ga[i] = (uint32_t)((min(m0 + r, M - 1) - m0) * K + (slot ^ lds_swz<CPR>(r)) * EPC) * (uint32_t)sizeof(TI);
     }
 #pragma unroll
     for (int i = 0; i < B_INS; ++i) {
       const int r = (wave * B_INS + i) * RPI + rl;
-      gb[i] = (const TI*)p.W + (size_t)(n0 + r) * K + (slot ^ lds_swz<CPR>(r)) * EPC;
+      gb[i] = (uint32_t)(r * K + (slot ^ lds_swz<CPR>(r)) * EPC) * (uint32_t)sizeof(TI);
     }
   }
   auto issue = [&](int kt, int stage) {
     char* sa = smem + stage * STAGE + wave * A_INS * 1024;
     char* sb = smem + stage * STAGE + A_BYTES + wave * B_INS * 1024;
-    const int k0 = kt * BK;
+    const char* ak = abase + (size_t)kt * BK * sizeof(TI);
+    const char* bk = bbase + (size_t)kt * BK * sizeof(TI);
 #pragma unroll
-    for (int i = 0; i < A_INS; ++i) dma16(ga[i] + k0, sa + i * 1024);
+    for (int i = 0; i < A_INS; ++i) dma16(ak + ga[i], sa + i * 1024);
 #pragma unroll
-    for (int i = 0; i < B_INS; ++i) dma16(gb[i] + k0, sb + i * 1024);
+    for (int i = 0; i < B_INS; ++i) dma16(bk + gb[i], sb + i * 1024);
   };
 
   // fragment addresses: row (lane & 31) of each 32-row sub-tile; the swizzle

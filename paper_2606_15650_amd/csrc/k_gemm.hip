@@ -122,20 +122,45 @@ struct DevParams {
 // (l & 31) and column (r/4)*8 + (l/32)*4 + r%4 of the block -- four
 // consecutive columns of one row per register quad.
 //
-// Epilogue staging: once the K loop is done, the operand LDS is reused; each
-// wave parks a 32-row strip of JP column blocks in row-major order (one 8- or
-// 16-byte write per register quad), then writes it back with 16-byte
-// row-contiguous accesses.  TS is the staged type: FP32 for the residual
-// epilogue (the residual is added before rounding), else TO.
-template <typename TO, int EPI, int TN, int NW, int SMEM>
+// Epilogue: once the K loop is done, the operand LDS is reused.  Each wave
+// forms its outputs -- bias, Q scaling, GELU or the residual (loaded in the
+// same layout, added in FP32, rounded once) -- and parks them in its own LDS
+// region in the output type, then writes the region back with 16-byte
+// row-contiguous stores.  Loads come before stores wherever possible: on
+// this architecture loads and stores share one counter, so a load issued
+// after a store waits for the store to be acknowledged.  The region holds
+// whole 32-row strips (see Staging::NS).  Rows are unpadded, with 16-byte chunks
+// XOR-permuted by the row (chunk c of row r in slot c ^ (r mod 16)) so that
+// the 32 rows a register quad spans land on distinct bank groups.
+template <typename TO, int EPI, int TM, int TN, int NW, int SMEM>
 struct Staging {
-  typedef typename std::conditional<EPI == EPI_RESID, float, TO>::type TS;
-  static constexpr int SPAD = 16 / (int)sizeof(TS);
-  static constexpr int bytes(int jp) { return NW * 32 * (jp * 32 + SPAD) * (int)sizeof(TS); }
-  static constexpr int JP = bytes(TN) <= SMEM ? TN : (bytes(TN / 2) <= SMEM ? TN / 2 : 1);
-  static constexpr int SROW = JP * 32 + SPAD;
-  static_assert(bytes(JP) <= SMEM && TN % JP == 0, "epilogue staging does not fit");
+  static constexpr int ROWB = TN * 32 * (int)sizeof(TO);        // bytes per staged row
+  static constexpr int CPR = ROWB / 16;                          // 16-byte chunks per row
+  static constexpr int SWZ = (CPR < 16 ? CPR : 16) - 1;
+  static constexpr int STRIP = 32 * ROWB;                        // one 32-row strip of one wave
+  static constexpr int FIT = SMEM / (NW * STRIP) < TM ? SMEM / (NW * STRIP) : TM;
+  // strips per pass: the residual epilogue loads, so it stages as much as
+  // fits before its first store; the others load nothing after the bias and
+  // go strip by strip, one strip's stores draining under the next's math
+  static constexpr int NS = EPI == EPI_RESID ? FIT : 1;
+  static_assert(NS >= 1 && CPR >= 4 && (CPR & (CPR - 1)) == 0, "epilogue staging does not fit");
+  static_assert((NS * 32 * CPR) % 64 == 0, "write-back covers whole waves");
 };
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T* p, float (&v)[4]);
+template <>
+__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
+  const floatx4 x = *(const floatx4*)p;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = x[e];
+}
+template <>
+__device__ __forceinline__ void ld4(const bf16_t* p, float (&v)[4]) {
+  const bf16x4 x = *(const bf16x4*)p;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = static_cast<float>(x[e]);
+}
 
 __device__ __forceinline__ void st4(float* p, const float (&v)[4]) { *(floatx4*)p = floatx4{v[0], v[1], v[2], v[3]}; }
 __device__ __forceinline__ void st4(bf16_t* p, const float (&v)[4]) {
@@ -156,30 +181,37 @@ __device__ __forceinline__ void st4(fp8_t* p, const float (&v)[4]) {
 template <typename TO, typename TR, int EPI, int TM, int TN, int NW, int SMEM>
 __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM][TN], char* smem, int wave, int lane,
                                          int wrow0, int wcol0) {
-  typedef Staging<TO, EPI, TN, NW, SMEM> SG;
-  typedef typename SG::TS TS;
-  constexpr int JP = SG::JP, SROW = SG::SROW;
+  typedef Staging<TO, EPI, TM, TN, NW, SMEM> SG;
+  constexpr int ROWB = SG::ROWB, CPR = SG::CPR, SWZ = SG::SWZ, NS = SG::NS;
   const int M = p.M, N = p.N;
-  TO* __restrict__ C = (TO*)p.C;
-  TS* stg = reinterpret_cast<TS*>(smem) + wave * 32 * SROW;
-  constexpr int CH = 16 / (int)sizeof(TS);  // staged elements per 16-byte chunk
-  constexpr int CPRS = JP * 32 / CH;        // chunks per staged row
+  char* stg = smem + wave * NS * SG::STRIP;
   const int lrow = lane & 31, lq = (lane >> 5) * 4;
+  // bias of the lane's columns (loaded before any store)
+  floatx4 bias[TN][4];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+  for (int j = 0; j < TN; ++j)
 #pragma unroll
-    for (int j0 = 0; j0 < TN; j0 += JP) {
-      // 1. stage columns [j0*32, (j0+JP)*32) of the strip's 32 rows
+    for (int q = 0; q < 4; ++q) bias[j][q] = *(const floatx4*)(p.bias + wcol0 + j * 32 + q * 8 + lq);
 #pragma unroll
-      for (int jj = 0; jj < JP; ++jj) {
+  for (int i0 = 0; i0 < TM; i0 += NS) {
+    // 1. outputs of strips [i0, i0 + NS) into LDS
+#pragma unroll
+    for (int is = 0; is < NS && i0 + is < TM; ++is) {
+      const int i = i0 + is;
+      const int srow = is * 32 + lrow;  // staged row
+      const int grow = min(wrow0 + i * 32 + lrow, M - 1);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int col = wcol0 + (j0 + jj) * 32 + q * 8 + lq;
-          const floatx4 b4 = *(const floatx4*)(p.bias + col);
+          const int cl = j * 32 + q * 8 + lq;  // column within the wave's block
+          const int col = wcol0 + cl;
+          float rv[4] = {0.f, 0.f, 0.f, 0.f};
+          if constexpr (EPI == EPI_RESID) ld4((const TR*)p.resid + (size_t)grow * N + col, rv);
           float v[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            float x = acc[i][j0 + jj][q * 4 + e] * p.acc_scale + b4[e];
+            float x = acc[i][j][q * 4 + e] * p.acc_scale + bias[j][q][e];
             if (EPI == EPI_BIAS) {
               if (col + e < p.qcols) x *= p.qscale;
             } else if (EPI == EPI_GELU) {
@@ -187,40 +219,31 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
               // FP8 output: the activation is a bf16 value first (as in the
               // BF16 path), then scaled and rounded to E4M3
               if (sizeof(TO) == 1) x = static_cast<float>(static_cast<bf16_t>(x)) * p.out_inv_scale;
+            } else {
+              x += rv[e];
             }
             v[e] = x;
           }
-          st4(stg + lrow * SROW + jj * 32 + q * 8 + lq, v);
+          const int byte = cl * (int)sizeof(TO);
+          const int chunk = (byte >> 4) ^ (srow & SWZ);
+          st4((TO*)(stg + srow * ROWB + chunk * 16 + (byte & 15)), v);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      // 2. write the rows back with 16-byte (staged) chunks
-      for (int c = lane; c < 32 * CPRS; c += 64) {
-        const int rr = c / CPRS, cc = c % CPRS;
-        const int grow = wrow0 + i * 32 + rr, gcol = wcol0 + j0 * 32 + cc * CH;
-        if (grow >= M) continue;
-        const TS* src = stg + rr * SROW + cc * CH;
-        if constexpr (EPI == EPI_RESID) {
-          // CH = 4 FP32 sums; add the residual, round once to the output type
-          const floatx4 s4 = *(const floatx4*)src;
-          const TR* rp = (const TR*)p.resid + (size_t)grow * N + gcol;
-          float rv[4];
-          if constexpr (sizeof(TR) == 2) {
-            const bf16x4 r4 = *(const bf16x4*)rp;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // 2. the strips back to memory, 16 bytes per lane, row-contiguous
+    constexpr int NCH = NS * 32 * CPR;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) rv[k] = static_cast<float>(r4[k]);
-          } else {
-            const floatx4 r4 = *(const floatx4*)rp;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) rv[k] = r4[k];
-          }
-          const float o[4] = {s4[0] + rv[0], s4[1] + rv[1], s4[2] + rv[2], s4[3] + rv[3]};
-          st4(C + (size_t)grow * N + gcol, o);
-        } else {
-          *(intx4*)(C + (size_t)grow * N + gcol) = *(const intx4*)src;
-        }
-      }
+    for (int c0 = 0; c0 < NCH; c0 += 64) {
+      const int c = c0 + lane;  // NCH is a multiple of 64
+      const int srow = c / CPR, cc = c % CPR;
+      const int i = i0 + srow / 32;  // past TM only in a last, partial pass
+      const int grow = wrow0 + i * 32 + (srow & 31);
+      const intx4 v = *(const intx4*)(stg + srow * ROWB + ((cc ^ (srow & SWZ)) * 16));
+      if (i < TM && grow < M) *(intx4*)((char*)p.C + ((size_t)grow * N + wcol0) * sizeof(TO) + cc * 16) = v;
+    }
+    if (i0 + NS < TM) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }

@@ -71,9 +71,11 @@ __device__ __forceinline__ void load_row(const bf16_t* src, int lane, float (&v)
   }
 }
 
+// LayerNorm of the row in v (lane-owned elements, RowMap order) with gain gv
+// and shift bv in the same order, written to row `row` of out (and out_q).
 template <int NPL>
-__device__ __forceinline__ void ln_store(float (&v)[NPL], const float* g, const float* b, float eps, int h,
-                                         int lane, size_t row, void* out, ElemType out_t, fp8_t* out_q,
+__device__ __forceinline__ void ln_store(float (&v)[NPL], const float (&gv)[NPL], const float (&bv)[NPL], float eps,
+                                         int h, int lane, size_t row, void* out, ElemType out_t, fp8_t* out_q,
                                          float q_inv_scale) {
   typedef RowMap<NPL> RM;
   float s = 0.f;
@@ -93,7 +95,8 @@ __device__ __forceinline__ void ln_store(float (&v)[NPL], const float* g, const 
     float y[RM::VEC];
     const int c0 = RM::col(c * RM::VEC, lane);
 #pragma unroll
-    for (int k = 0; k < RM::VEC; ++k) y[k] = g[c0 + k] * ((v[c * RM::VEC + k] - mean) * rstd) + b[c0 + k];
+    for (int k = 0; k < RM::VEC; ++k)
+      y[k] = gv[c * RM::VEC + k] * ((v[c * RM::VEC + k] - mean) * rstd) + bv[c * RM::VEC + k];
     if (out_t == ET_F32) {
 #pragma unroll
       for (int k = 0; k < RM::VEC; ++k) ((float*)out)[row * h + c0 + k] = y[k];
@@ -139,7 +142,10 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
   load_row<NPL>(pos + (size_t)p * h, lane, w);
 #pragma unroll
   for (int i = 0; i < NPL; ++i) v[i] += w[i];
-  ln_store<NPL>(v, g, b, eps, h, lane, t, out, out_t, out_q, q_inv_scale);
+  float gv[NPL], bv[NPL];
+  load_row<NPL>(g, lane, gv);
+  load_row<NPL>(b, lane, bv);
+  ln_store<NPL>(v, gv, bv, eps, h, lane, t, out, out_t, out_q, q_inv_scale);
 }
 
 template <typename TY, int NPL>
@@ -150,12 +156,84 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const TY* __restrict__ y
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
   constexpr int h = NPL * 64;
-  float v[NPL];
+  float v[NPL], gv[NPL], bv[NPL];
   load_row<NPL>(y + (size_t)row * h, lane, v);
-  ln_store<NPL>(v, g, b, eps, h, lane, row, out, out_t, out_q, q_inv_scale);
+  load_row<NPL>(g, lane, gv);
+  load_row<NPL>(b, lane, bv);
+  ln_store<NPL>(v, gv, bv, eps, h, lane, row, out, out_t, out_q, q_inv_scale);
 }
 
 constexpr int kMaxLabels = 64;
+
+// Token classifier on the FP32 matrix cores (C <= 32 labels): one wave forms
+// z^T = Wc x^T for 32 tokens with v_mfma_f32_32x32x2_f32, exact products of
+// the FP32 head and the (bf16 or FP32) hidden state, FP32 sums.  Lane half hh
+// feeds the k-index hh of every MFMA from its own 16-element slice of each
+// 32-column chunk.  Then lane l holds the logits of token (l & 31) for
+// classes (r/4)*8 + hh*4 + r%4 of register r; the two halves merge their
+// top-2 with one exchange (ties to the lowest class index).
+template <typename TX, int H>
+__global__ __launch_bounds__(256) void classifier_mfma_kernel(const TX* __restrict__ x, const float* __restrict__ wc,
+                                                              const float* __restrict__ bc, int T, int C,
+                                                              uint8_t* __restrict__ labels,
+                                                              float* __restrict__ logits, float* __restrict__ margin) {
+  const int lane = threadIdx.x & 63;
+  const int t0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+  if (t0 >= T) return;
+  const int hh = lane >> 5, r32 = lane & 31;
+  const int tok = min(t0 + r32, T - 1);  // rows past T re-read row T-1, never stored
+  const bool cvalid = r32 < C;
+  const TX* xr = x + (size_t)tok * H + hh * 16;
+  const float* wr = wc + (size_t)(cvalid ? r32 : 0) * H + hh * 16;
+  floatx16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int kc = 0; kc < H / 32; ++kc) {
+    float xv[16], wv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) xv[e] = ldf(xr + kc * 32 + e);
+#pragma unroll
+    for (int e = 0; e < 16; e += 4) {
+      const floatx4 w4 = *(const floatx4*)(wr + kc * 32 + e);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wv[e + k] = cvalid ? w4[k] : 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wv[e], xv[e], acc, 0, 0, 0);
+  }
+  float best = -INFINITY, second = -INFINITY;
+  int arg = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int c = (r >> 2) * 8 + hh * 4 + (r & 3);  // increasing in r
+    if (c < C) {
+      const float z = acc[r] + bc[c];
+      if (logits && t0 + r32 < T) logits[(size_t)(t0 + r32) * C + c] = z;
+      if (z > best) {
+        second = best;
+        best = z;
+        arg = c;
+      } else if (z > second) {
+        second = z;
+      }
+    }
+  }
+  const float ob = __shfl_xor(best, 32, 64), os = __shfl_xor(second, 32, 64);
+  const int oa = __shfl_xor(arg, 32, 64);
+  if (hh == 0 && t0 + r32 < T) {
+    float b1, b2;
+    int a1;
+    if (best > ob) {
+      b1 = best, a1 = arg, b2 = fmaxf(second, ob);
+    } else if (ob > best) {
+      b1 = ob, a1 = oa, b2 = fmaxf(os, best);
+    } else {
+      b1 = best, a1 = min(arg, oa), b2 = best;
+    }
+    labels[t0 + r32] = (uint8_t)a1;
+    if (margin) margin[t0 + r32] = C > 1 ? b1 - b2 : INFINITY;
+  }
+}
 
 template <typename TX, int NPL>
 __global__ __launch_bounds__(256) void classifier_kernel(const TX* __restrict__ x, const float* __restrict__ wc,
@@ -298,18 +376,41 @@ void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const 
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
                       void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
   if (rows <= 0) return;
+  const int blocks = ceil_div(rows, 4);
   if (y_t == ET_F32) {
-    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0,
-                                               s, (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL>), dim3(blocks), dim3(256), 0, s,
+                                               (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
   } else {
-    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL>), dim3(ceil_div(rows, 4)), dim3(256), 0,
-                                               s, (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL>), dim3(blocks), dim3(256), 0, s,
+                                               (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
   }
 }
 
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
                        uint8_t* labels, float* logits, float* margin, hipStream_t s) {
   if (T <= 0) return;
+  if (C <= 32) {
+    const int blocks = ceil_div(ceil_div(T, 32), 4);
+#define ANON_CLS_MFMA(HV)                                                                                        \
+  case HV:                                                                                                       \
+    if (x_t == ET_F32)                                                                                           \
+      hipLaunchKernelGGL((classifier_mfma_kernel<float, HV>), dim3(blocks), dim3(256), 0, s, (const float*)x,    \
+                         wc_t, bc, T, C, labels, logits, margin);                                                \
+    else                                                                                                         \
+      hipLaunchKernelGGL((classifier_mfma_kernel<bf16_t, HV>), dim3(blocks), dim3(256), 0, s, (const bf16_t*)x,  \
+                         wc_t, bc, T, C, labels, logits, margin);                                                \
+    return;
+    switch (h) {
+      ANON_CLS_MFMA(128)
+      ANON_CLS_MFMA(256)
+      ANON_CLS_MFMA(512)
+      ANON_CLS_MFMA(768)
+      ANON_CLS_MFMA(1024)
+      default:
+        break;
+    }
+#undef ANON_CLS_MFMA
+  }
   if (x_t == ET_F32) {
     ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((classifier_kernel<float, NPL>), dim3(ceil_div(T, 4)), dim3(256), 0,
                                                s, (const float*)x, wc_t, bc, T, C, labels, logits, margin));

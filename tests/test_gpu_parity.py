@@ -450,3 +450,34 @@ def test_tiny_fp8_matches_rounding_oracle(torch_dev, tiny_batch):
         f"label agreement vs pure {(lab == lp).mean():.4f}")
     bad, n = confident_labels_agree(lab, lq, mq)
     assert len(bad) == 0, (len(bad), n)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_classifier_ties_and_margins(torch_dev, tiny_batch, precision):
+    """Argmax ties go to the lowest class index with margin 0; margins follow
+    the oracle's top-1 minus top-2 (the head is FP32 on every path)."""
+    from paper_2606_15650_amd import api
+    W = synth.make_weights(TINY, 0)
+    W["wc"] = W["wc"].copy()
+    W["bc"] = W["bc"].copy()
+    # classes 3 and 5: identical head rows and a bias that puts them on top
+    W["wc"][:, 5] = W["wc"][:, 3]
+    W["bc"][3] = W["bc"][5] = 8.0
+    m = api.Model(TINY, synth.weights_blob(TINY, W), precision)
+    lab, z, mg = _run_ner(m, tiny_batch)
+    say(f"[classifier {precision}] tie: labels {np.unique(lab)}, max margin {mg.max():.3e}")
+    assert (lab == 3).all()
+    assert (mg == 0).all()
+    assert np.array_equal(z[:, 3], z[:, 5])
+    m.close()
+    # no tie: class 3 alone on top; margins against the oracle's
+    W["bc"][5] = 0.0
+    m = api.Model(TINY, synth.weights_blob(TINY, W), precision)
+    lab, z, mg = _run_ner(m, tiny_batch)
+    prec = None if precision == "fp32" else encoder.Precision(precision)
+    zr, lr, mr = encoder.forward(W, TINY, tiny_batch.ids, tiny_batch.cu_seqlens, prec)
+    assert (lab == 3).all() and (lr == 3).all()
+    err = np.abs(mg - mr).max()
+    say(f"[classifier {precision}] max |margin - oracle| {err:.3e}")
+    assert err <= (1e-4 if precision == "fp32" else 5e-3) * max(1.0, np.abs(zr).max())
+    m.close()

@@ -18,7 +18,10 @@ FP32_LOGIT_RTOL = 1e-4
 # rounding, moves by up to 0.017 (tests/golden/sensitivity_base_bf16.json):
 # no bf16 implementation can be held closer, so the bound is 0.03 and the
 # label margin 0.06; agreement above 1e-2 is still measured and reported.
-REDUCED_GATE = {("bf16", 2): (5e-3, 1e-2), ("fp8", 2): (5e-3, 1e-2), ("bf16", 12): (3e-2, 6e-2)}
+# At 24 layers with FP8 GEMM inputs the same probe moves the logits by up to
+# 0.21 (tests/golden/sensitivity_large_fp8.json): bound 0.3, margin 0.6.
+REDUCED_GATE = {("bf16", 2): (5e-3, 1e-2), ("fp8", 2): (5e-3, 1e-2), ("bf16", 12): (3e-2, 6e-2),
+                ("fp8", 24): (3e-1, 6e-1)}
 
 
 def say(*a):

@@ -10,7 +10,7 @@ import pytest
 
 import synth
 from oracle import encoder, pipeline as opipe, pseudonym as ops, spans as ospans
-from synth.configs import TINY, BASE, ModelConfig
+from synth.configs import TINY, BASE, LARGE, ModelConfig
 from tests.gpu_common import (MARGIN, FP32_LOGIT_RTOL, REDUCED_GATE, confident_labels_agree, confident_records,
                               logit_rel_err,
                               make_cache, make_model, say)
@@ -480,4 +480,34 @@ def test_classifier_ties_and_margins(torch_dev, tiny_batch, precision):
     err = np.abs(mg - mr).max()
     say(f"[classifier {precision}] max |margin - oracle| {err:.3e}")
     assert err <= (1e-4 if precision == "fp32" else 5e-3) * max(1.0, np.abs(zr).max())
+    m.close()
+
+
+def test_large_fp8_sampled_records(torch_dev):
+    """24-layer h1024 encoder with FP8-E4M3 GEMM inputs (the large FP8 workload's
+    model, scales and length distribution): a 16-record batch with autotuned
+    tiles, two sampled records against the FP8-rounding oracle, alone == in batch."""
+    wl = synth.workload("large_fp8")
+    scales = np.asarray(_fp8_scales("large_fp8"), np.float32).reshape(-1)
+    W, m = make_model(LARGE, "fp8", wl.weight_seed, o_target=wl.o_target, act_scales=scales)
+    rb = synth.generate_records(16, wl.lengths, LARGE.n_types, LARGE.vocab, wl.seed)
+    from paper_2606_15650_amd.pipeline import Pipeline
+    Pipeline(m).autotune(rb.n_tokens, rb.n_records)
+    lab, z, mg = _run_ner(m, rb)
+    bound, tau = REDUCED_GATE[("fp8", LARGE.n_layers)]
+    prec = encoder.Precision("fp8", act_scales=_fp8_scales("large_fp8"))
+    L = np.diff(rb.cu_seqlens)
+    for r in (int(np.argmin(L)), int(np.argsort(L)[len(L) // 2])):
+        a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
+        sub = rb.subset([r])
+        say(f"[large fp8] record {r}: {b - a} tokens vs fp8-rounding oracle")
+        zq, lq, mq = encoder.forward(W, LARGE, sub.ids, sub.cu_seqlens, prec)
+        dev = np.abs(z[a:b] - zq).max()
+        bad, n = confident_labels_agree(lab[a:b], lq, mq)
+        say(f"  max |z - z_oracle| {dev:.3e} (bound {bound}); labels differ above margin 1e-2 on "
+            f"{len(bad)} of {n} tokens")
+        assert dev < bound
+        assert ((lab[a:b] != lq) & (mq > tau)).sum() == 0
+        l1, z1, _ = _run_ner(m, sub)
+        np.testing.assert_array_equal(z1, z[a:b])
     m.close()

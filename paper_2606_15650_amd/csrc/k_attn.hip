@@ -259,8 +259,11 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
   const int ld = 3 * hidden;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5;
 
-  __shared__ bf16_t Ks[RMAX * KS];
-  __shared__ bf16_t Vt[D * VS];
+  // V^T first: its reads then sit below 64 KB, within reach of the
+  // instructions' immediate offsets
+  __shared__ __align__(16) bf16_t lds[D * VS + RMAX * KS];
+  bf16_t* const Vt = lds;
+  bf16_t* const Ks = lds + D * VS;
 
   const int Lp = (L + 31) & ~31;  // keys padded with zeros to whole 32-key blocks
   for (int c = tid; c < Lp * 8; c += WAVES * 64) {

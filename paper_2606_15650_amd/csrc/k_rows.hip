@@ -148,22 +148,31 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
   ln_store<NPL>(v, gv, bv, eps, h, lane, t, out, out_t, out_q, q_inv_scale);
 }
 
-template <typename TY, int NPL>
+// RPW rows per wave: every row's loads are issued before the first
+// reduction, so more bytes are in flight per wave.
+template <typename TY, int NPL, int RPW>
 __global__ __launch_bounds__(256) void layernorm_kernel(const TY* __restrict__ y, const float* __restrict__ g,
                                                         const float* __restrict__ b, float eps, int rows, void* out,
                                                         ElemType out_t, fp8_t* out_q, float q_inv_scale) {
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+  if (row0 >= rows) return;
   constexpr int h = NPL * 64;
-  float v[NPL], gv[NPL], bv[NPL];
-  load_row<NPL>(y + (size_t)row * h, lane, v);
+  float v[RPW][NPL], gv[NPL], bv[NPL];
+#pragma unroll
+  for (int k = 0; k < RPW; ++k)
+    if (row0 + k < rows) load_row<NPL>(y + (size_t)(row0 + k) * h, lane, v[k]);
   load_row<NPL>(g, lane, gv);
   load_row<NPL>(b, lane, bv);
-  ln_store<NPL>(v, gv, bv, eps, h, lane, row, out, out_t, out_q, q_inv_scale);
+#pragma unroll
+  for (int k = 0; k < RPW; ++k)
+    if (row0 + k < rows) ln_store<NPL>(v[k], gv, bv, eps, h, lane, row0 + k, out, out_t, out_q, q_inv_scale);
 }
 
 constexpr int kMaxLabels = 64;
+#ifndef ANON_LN_RPW
+#define ANON_LN_RPW 2
+#endif
 
 // Token classifier on the FP32 matrix cores (C <= 32 labels): one wave forms
 // z^T = Wc x^T for 32 tokens with v_mfma_f32_32x32x2_f32, exact products of
@@ -376,12 +385,13 @@ void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const 
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
                       void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
   if (rows <= 0) return;
-  const int blocks = ceil_div(rows, 4);
+  constexpr int RPW = ANON_LN_RPW;
+  const int blocks = ceil_div(rows, 4 * RPW);
   if (y_t == ET_F32) {
-    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL>), dim3(blocks), dim3(256), 0, s,
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL, RPW>), dim3(blocks), dim3(256), 0, s,
                                                (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
   } else {
-    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL>), dim3(blocks), dim3(256), 0, s,
+    ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL, RPW>), dim3(blocks), dim3(256), 0, s,
                                                (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
   }
 }

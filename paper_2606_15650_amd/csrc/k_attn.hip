@@ -4,13 +4,16 @@
 // the same record only (bidirectional encoder attention).  Q already carries
 // the 1/sqrt(d) = 1/8 factor (applied exactly in the QKV GEMM epilogue).
 //
-// Work item = (q-block of 32*WAVES rows of one record, head).  The block
-// streams the record's keys in tiles of 64: K rows and V^T are staged in LDS
-// and shared by all waves; each wave owns 32 query rows and computes
-// S^T = K Q^T with 32x32 MFMAs, so that every lane holds the scores of one
-// query row.  Records longer than one tile take two passes over their keys:
-// the first finds each row's exact maximum, the second forms
-// p = exp(s - max) once (FP32, base-2 exponentials), sums it in FP32, rounds
+// Two kernels.  BF16 operands (records of at most 512 keys): one workgroup
+// per (record, head) holds the record's whole K and V^T in LDS
+// (attn_resident_kernel, below).  FP32 operands: work item = (q-block of
+// 32*WAVES rows of one record, head); the block streams the record's keys in
+// tiles of 64, K rows and V^T staged in LDS.  In both, each wave owns 32
+// query rows and computes S^T = K Q^T with 32x32 MFMAs, so that every lane
+// holds the scores of one query row.  Records longer than one key block take
+// two passes over their keys: the first finds each row's exact maximum, the
+// second forms p = exp(s - max) once (FP32, base-2 exponentials), sums it in
+// FP32, rounds
 // it to the operand type and accumulates O^T += V^T P^T in FP32.  Rounding p
 // relative to the final maximum (not a running one) makes the rounded values
 // a function of the record alone, identical to the definition
@@ -238,9 +241,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
 // 32 lanes on distinct banks.  Records are binned by length so that RMAX and
 // the wave count follow the record (see kClassMax).
-// PAIR: two independent key blocks per iteration (more MFMA chains in flight
-// per wave, at the cost of registers).
-template <typename TO, int RMAX, int WAVES, bool PAIR>
+template <typename TO, int RMAX, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
                                                                    TO* __restrict__ out,
                                                                    const int4* __restrict__ recs,
@@ -309,17 +310,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
     // maximum of the scaled scores is the scaled maximum)
     float mraw = -INFINITY;
     if (nkb > 1) {
-      int kb = 0;
-      if (PAIR) {
-        for (; kb + 1 < nkb; kb += 2) {
-          floatx16 s0, s1;
-          qk(kb, s0);
-          qk(kb + 1, s1);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, fmaxf(s0[r], s1[r]));
-        }
-      }
-      for (; kb < nkb; ++kb) {
+      for (int kb = 0; kb < nkb; ++kb) {
         floatx16 s0;
         qk(kb, s0);
 #pragma unroll
@@ -327,9 +318,9 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
       }
       mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
     }
-    floatx16 o[2], o2[2];
+    floatx16 o[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = o2[0][r] = o2[1][r] = 0.f;
+    for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
     float lsum = 0.f;
     // pass 2: p = 2^(s*log2(e) - max*log2(e)) = exp(s - max), O^T += V^T P^T
     auto pv = [&](int kb, floatx16& s, floatx16 (&acc)[2]) {
@@ -350,17 +341,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
         }
       }
     };
-    int kb = 0;
-    if (PAIR) {
-      for (; kb + 1 < nkb; kb += 2) {
-        floatx16 s0, s1;
-        qk(kb, s0);
-        qk(kb + 1, s1);
-        pv(kb, s0, o);
-        pv(kb + 1, s1, o2);
-      }
-    }
-    for (; kb < nkb; ++kb) {
+    for (int kb = 0; kb < nkb; ++kb) {
       floatx16 s0;
       qk(kb, s0);
       if (nkb == 1) {
@@ -369,13 +350,6 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
         mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
       }
       pv(kb, s0, o);
-    }
-    if (PAIR) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        o[0][r] += o2[0][r];
-        o[1][r] += o2[1][r];
-      }
     }
     const float ltot = lsum + __shfl_xor(lsum, 32, 64);
     const float inv = 1.0f / ltot;
@@ -456,13 +430,13 @@ template <typename TO>
 void launch_resident(const bf16_t* q, TO* out, const int4* items, int per_class, const int* counts, int n_heads,
                      int hidden, float out_inv_scale, hipStream_t s) {
   const dim3 grid(per_class, n_heads);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 128, 4, false>), grid, dim3(4 * 64), 0, s, q, out, items, counts,
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 128, 4>), grid, dim3(4 * 64), 0, s, q, out, items, counts,
                      hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 256, 8, false>), grid, dim3(8 * 64), 0, s, q, out,
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 256, 8>), grid, dim3(8 * 64), 0, s, q, out,
                      items + per_class, counts + 1, hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 384, 12, false>), grid, dim3(12 * 64), 0, s, q, out,
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 384, 12>), grid, dim3(12 * 64), 0, s, q, out,
                      items + 2 * per_class, counts + 2, hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 512, 16, false>), grid, dim3(16 * 64), 0, s, q, out,
+  hipLaunchKernelGGL((attn_resident_kernel<TO, 512, 16>), grid, dim3(16 * 64), 0, s, q, out,
                      items + 3 * per_class, counts + 3, hidden, out_inv_scale);
 }
 

@@ -2,11 +2,14 @@
 // token-classification head (argmax and top-2 margin), type conversions and
 // the window gather / owner-window merge for long records.
 //
-// One 64-lane wave owns one token row; lane i holds elements i, i+64, ...
-// so every load and store is a contiguous 256-byte wave access.  LayerNorm
-// statistics are FP32 and two-pass (mean, then mean of squared deviations)
-// with a fixed butterfly reduction order, so a row's result never depends on
-// the other rows of the batch.
+// A 64-lane wave owns a token row (LayerNorm: two rows); lane i holds VEC
+// consecutive elements (4 where the row length allows) of each chunk of
+// 64*VEC elements, so every load and store is a contiguous wave access (see
+// RowMap).  LayerNorm statistics are
+// FP32 and two-pass (mean, then mean of squared deviations) with a fixed
+// butterfly reduction order, so a row's result never depends on the other
+// rows of the batch.  The classifier runs on the FP32 matrix cores, 32
+// tokens per wave.
 #include <algorithm>
 
 #include "kernels.hpp"

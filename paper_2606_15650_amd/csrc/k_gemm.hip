@@ -609,7 +609,8 @@ struct Cfg {
   X(7, 128, 256, 32, 2, 4, 3, 2, "bf16_128x256x32_w2x4_s3")    \
   X(8, 256, 256, 64, 4, 2, 2, 1, "bf16_256x256x64_w4x2_s2")    \
   X(9, 256, 256, 32, 4, 2, 4, 1, "bf16_256x256x32_w4x2_s4")    \
-  X(10, 256, 128, 32, 4, 2, 4, 1, "bf16_256x128x32_w4x2_s4")
+  X(10, 256, 128, 32, 4, 2, 4, 1, "bf16_256x128x32_w4x2_s4")    \
+  X(11, 256, 256, 64, 2, 4, 2, 1, "bf16_256x256x64_w2x4_s2")
 #define ANON_F32_CFGS(X)                                 \
   X(0, 128, 128, 32, 2, 2, 0, 2, "f32_128x128x32_w2x2") \
   X(1, 64, 64, 32, 2, 2, 0, 2, "f32_64x64x32_w2x2")     \
@@ -622,7 +623,8 @@ struct Cfg {
   X(3, 256, 128, 128, 4, 2, 3, 1, "fp8_256x128x128_w4x2_s3") \
   X(4, 256, 128, 64, 4, 2, 3, 2, "fp8_256x128x64_w4x2_s3")  \
   X(5, 128, 256, 64, 2, 4, 3, 2, "fp8_128x256x64_w2x4_s3")  \
-  X(6, 256, 256, 64, 4, 2, 4, 1, "fp8_256x256x64_w4x2_s4")
+  X(6, 256, 256, 64, 4, 2, 4, 1, "fp8_256x256x64_w4x2_s4")  \
+  X(7, 256, 256, 128, 2, 4, 2, 1, "fp8_256x256x128_w2x4_s2")
 
 #define ANON_CFG_ROW(i, bm, bn, bk, wgm, wgn, st, occ, name) {bm, bn, bk, wgm, wgn, st, occ, name},
 const Cfg kCfgBF16[] = {ANON_BF16_CFGS(ANON_CFG_ROW)};
@@ -723,7 +725,7 @@ int default_gemm_config(const GemmParams& g) {
   // the preferred tile of the type if it divides the shape, else the first
   // one that does
   const int n = gemm_num_configs(g.in);
-  const int pref = g.in == ET_BF16 ? 8 : (g.in == ET_FP8 ? 2 : 0);
+  const int pref = g.in == ET_BF16 ? 11 : (g.in == ET_FP8 ? 7 : 0);
   if (gemm_config_fits(g.in, pref, g.N, g.K)) return pref;
   for (int c = 0; c < n; ++c)
     if (gemm_config_fits(g.in, c, g.N, g.K)) return c;

@@ -241,8 +241,17 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
 // 32 lanes on distinct banks.  Records are binned by length so that RMAX and
 // the wave count follow the record (see kClassMax).
+// LDS bytes of a record-resident workgroup (V^T rows padded by 12 keys, K
+// rows by 8 elements) and the waves per SIMD that as many workgroups as fit
+// in the 160 KB of a CU's LDS bring; the register budget is held to that
+// occupancy.
+constexpr int resident_lds_bytes(int rmax) { return (D * (rmax + 12) + rmax * (D + 8)) * 2; }
+constexpr int resident_waves_per_eu(int rmax, int waves) {
+  return (163840 / resident_lds_bytes(rmax)) * waves / 4;
+}
+
 template <typename TO, int RMAX, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
+__global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
                                                                    TO* __restrict__ out,
                                                                    const int4* __restrict__ recs,
                                                                    const int* __restrict__ n_recs, int hidden,
@@ -263,34 +272,54 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
   // V^T first: its reads then sit below 64 KB, within reach of the
   // instructions' immediate offsets
   __shared__ __align__(16) bf16_t lds[D * VS + RMAX * KS];
+  static_assert(sizeof(lds) == resident_lds_bytes(RMAX), "LDS size");
   bf16_t* const Vt = lds;
   bf16_t* const Ks = lds + D * VS;
 
+  // A workgroup has one wave per 32 keys of the class bound, so every thread
+  // stages exactly NSTG 16-byte chunks of K and of V, and every wave owns at
+  // most one 32-row query chunk.  All of the thread's loads (its K and V
+  // chunks and its wave's Q fragments) are issued before the first LDS
+  // write, so the workgroup waits for one memory round trip, not one per
+  // chunk.
+  constexpr int NT = WAVES * 64;
+  constexpr int NSTG = RMAX * 8 / NT;
+  static_assert(RMAX == 32 * WAVES && NSTG * NT == RMAX * 8, "one wave per 32 keys");
   const int Lp = (L + 31) & ~31;  // keys padded with zeros to whole 32-key blocks
-  for (int c = tid; c < Lp * 8; c += WAVES * 64) {
-    const int r = c >> 3, cc = c & 7;
-    intx4 kv = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
+  intx4 kv[NSTG], vv[NSTG];
+#pragma unroll
+  for (int i = 0; i < NSTG; ++i) {
+    const int c = tid + i * NT, r = c >> 3, cc = c & 7;
+    kv[i] = intx4{0, 0, 0, 0};
+    vv[i] = intx4{0, 0, 0, 0};
     if (r < L) {
       const bf16_t* src = qkv + (size_t)(base + r) * ld + head * D + cc * 8;
-      kv = *(const intx4*)(src + hidden);
-      vv = *(const intx4*)(src + 2 * hidden);
+      kv[i] = *(const intx4*)(src + hidden);
+      vv[i] = *(const intx4*)(src + 2 * hidden);
     }
-    *(intx4*)&Ks[r * KS + cc * 8] = kv;
-    const bf16_t* ve = (const bf16_t*)&vv;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) Vt[(cc * 8 + e) * VS + r] = ve[e];
   }
-  __syncthreads();
-
   const int nkb = Lp / 32;
   const int nqc = (L + 31) / 32;
   const bool partial = (L & 31) != 0;  // only the last key block has missing keys
-  for (int qc = wave; qc < nqc; qc += WAVES) {
-    const int qrow = qc * 32 + (lane & 31);
-    frag qf[D / 16];
+  const int qc = wave;
+  const int qrow = qc * 32 + (lane & 31);
+  frag qf[D / 16];
 #pragma unroll
-    for (int kk = 0; kk < D / 16; ++kk)
-      qf[kk] = qrow < L ? *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * 16 + hh * 8) : frag{};
+  for (int kk = 0; kk < D / 16; ++kk)
+    qf[kk] = qrow < L ? *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * 16 + hh * 8) : frag{};
+#pragma unroll
+  for (int i = 0; i < NSTG; ++i) {
+    const int c = tid + i * NT, r = c >> 3, cc = c & 7;
+    if (r < Lp) {
+      *(intx4*)&Ks[r * KS + cc * 8] = kv[i];
+      const bf16_t* ve = (const bf16_t*)&vv[i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Vt[(cc * 8 + e) * VS + r] = ve[e];
+    }
+  }
+  __syncthreads();
+
+  if (qc < nqc) {
     // raw scores S^T of key block kb; missing keys of the last block -> -inf
     auto qk = [&](int kb, floatx16& s) {
 #pragma unroll
@@ -308,16 +337,31 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
     };
     // pass 1: row maximum of the raw scores (the scale is positive, so the
     // maximum of the scaled scores is the scaled maximum)
+    // Both passes are software-pipelined two blocks deep: block kb+1's QK^T
+    // MFMAs are issued before block kb's VALU work (maximum, exponentials),
+    // which then runs while the matrix core is busy.  Blocks are still
+    // consumed in key order, so sums and results do not change.
     float mraw = -INFINITY;
-    if (nkb > 1) {
-      for (int kb = 0; kb < nkb; ++kb) {
-        floatx16 s0;
-        qk(kb, s0);
+    auto rowmax = [&](const floatx16& s) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s0[r]);
+      for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s[r]);
+    };
+    floatx16 sa, sb;
+    qk(0, sa);
+    if (nkb > 1) {
+      for (int kb = 0; kb < nkb; kb += 2) {
+        if (kb + 1 < nkb) qk(kb + 1, sb);
+        rowmax(sa);
+        if (kb + 1 < nkb) {
+          if (kb + 2 < nkb) qk(kb + 2, sa);
+          rowmax(sb);
+        }
       }
-      mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
+      qk(0, sa);
+    } else {
+      rowmax(sa);
     }
+    mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
     floatx16 o[2];
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
@@ -341,15 +385,14 @@ __global__ __launch_bounds__(WAVES * 64) void attn_resident_kernel(const bf16_t*
         }
       }
     };
-    for (int kb = 0; kb < nkb; ++kb) {
-      floatx16 s0;
-      qk(kb, s0);
-      if (nkb == 1) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s0[r]);
-        mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
+    // sa holds block 0's scores
+    for (int kb = 0; kb < nkb; kb += 2) {
+      if (kb + 1 < nkb) qk(kb + 1, sb);
+      pv(kb, sa, o);
+      if (kb + 1 < nkb) {
+        if (kb + 2 < nkb) qk(kb + 2, sa);
+        pv(kb + 1, sb, o);
       }
-      pv(kb, s0, o);
     }
     const float ltot = lsum + __shfl_xor(lsum, 32, 64);
     const float inv = 1.0f / ltot;

@@ -110,6 +110,33 @@ def test_edge_lengths_one_token_and_max_pos(torch_dev):
         assert logit_rel_err(z, zr).max() <= FP32_LOGIT_RTOL
 
 
+def test_bf16_attention_length_classes_and_block_counts(torch_dev):
+    """BF16 attention keeps each record's K and V^T in LDS, in one of four
+    kernels by length (at most 128, 256, 384, 512 keys), and walks 32-key
+    blocks two at a time.  Lengths at and around every class bound, with
+    partial and whole last blocks and 1 to 16 blocks of both parities, agree
+    with the bf16-rounding oracle, and each record alone gives the bits it
+    gives inside the packed batch."""
+    cfg = ModelConfig(n_layers=2, hidden=128, n_heads=2, ffn=256, vocab=500, n_labels=9, max_pos=512)
+    W, m = make_model(cfg, "bf16", 4)
+    lens = [1, 31, 32, 33, 64, 96, 127, 128, 129, 160, 255, 256, 257, 320, 383, 384, 385, 448, 511, 512]
+    say(f"[edge bf16] lengths {lens}")
+    rb = synth.generate_records(len(lens), np.array(lens), 4, cfg.vocab, 6)
+    lab, z, mg = _run_ner(m, rb)
+    zq, lq, mq = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens, encoder.Precision("bf16"))
+    err = np.abs(z - zq).max()
+    say(f"  max |z - z_bf16oracle| {err:.3e}")
+    assert err < 5e-3
+    bad, n = confident_labels_agree(lab, lq, mq)
+    assert len(bad) == 0, (len(bad), n)
+    for r in (0, 3, 8, 11, 16, 19):
+        sub = rb.subset([r])
+        l1, z1, _ = _run_ner(m, sub)
+        a, b = rb.cu_seqlens[r], rb.cu_seqlens[r + 1]
+        np.testing.assert_array_equal(z1, z[a:b], err_msg=f"record of {lens[r]} tokens")
+        np.testing.assert_array_equal(l1, lab[a:b])
+
+
 def test_empty_batch_is_a_no_op(tiny_fp32):
     import torch
     from paper_2606_15650_amd import api

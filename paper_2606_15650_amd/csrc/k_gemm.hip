@@ -78,7 +78,9 @@ __device__ __forceinline__ float gelu_erf(float v) {
                     0.5f * 0.284496736f) * t + 0.5f * 0.254829592f) * t;
   const float sv = v * 0.84932180028801904f;
   const float r = v * (P * __builtin_amdgcn_exp2f(-(sv * sv)));
-  return v >= 0.0f ? v - r : r;
+  // v - r for v >= 0 and r for v < 0: since q <= 1/2, r = v q lies between
+  // 0 and v/2, so the wanted value is always the larger of the two
+  return fmaxf(v - r, r);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a

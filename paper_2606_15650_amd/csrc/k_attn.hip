@@ -337,10 +337,9 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
     };
     // pass 1: row maximum of the raw scores (the scale is positive, so the
     // maximum of the scaled scores is the scaled maximum)
-    // Both passes are software-pipelined two blocks deep: block kb+1's QK^T
-    // MFMAs are issued before block kb's VALU work (maximum, exponentials),
-    // which then runs while the matrix core is busy.  Blocks are still
-    // consumed in key order, so sums and results do not change.
+    // Both passes are software-pipelined two blocks deep: the next block's
+    // QK^T MFMAs are issued before the current block's VALU work (maximum,
+    // exponentials), which then runs while the matrix core is busy.
     float mraw = -INFINITY;
     auto rowmax = [&](const floatx16& s) {
 #pragma unroll
@@ -357,11 +356,16 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
           rowmax(sb);
         }
       }
-      qk(0, sa);
     } else {
       rowmax(sa);
     }
+    // sa and sb now hold the raw scores of the last two blocks, nkb-2 and
+    // nkb-1 (sa holds nkb-1 when nkb is odd), or sa holds block 0 alone
     mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
+    // K fragments are read from LDS again in pass 2 rather than kept live
+    // across pass 1 (no instruction: it only stops the compiler from reusing
+    // pass-1 loads, which would cost registers it does not have)
+    __asm__ volatile("" ::: "memory");
     floatx16 o[2];
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
@@ -385,15 +389,31 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
         }
       }
     };
-    // sa holds block 0's scores
-    for (int kb = 0; kb < nkb; kb += 2) {
-      if (kb + 1 < nkb) qk(kb + 1, sb);
-      pv(kb, sa, o);
-      if (kb + 1 < nkb) {
-        if (kb + 2 < nkb) qk(kb + 2, sa);
-        pv(kb + 1, sb, o);
+    // Pass 2 takes the blocks in the order nkb-2, nkb-1 (still in registers,
+    // not recomputed), then 0 .. nkb-3: a fixed order given by the record's
+    // length alone.  X holds the first block of the order, Y the second.
+    auto pass2 = [&](floatx16& X, floatx16& Y) {
+      const int first = nkb > 1 ? nkb - 2 : 0;
+      auto seq = [&](int i) { return i < 2 ? first + i : i - 2; };
+      pv(seq(0), X, o);
+      for (int i = 1; i < nkb; i += 2) {
+        if (i + 1 < nkb) qk(seq(i + 1), X);
+        pv(seq(i), Y, o);
+        if (i + 1 < nkb) {
+          if (i + 2 < nkb) qk(seq(i + 2), Y);
+          pv(seq(i + 1), X, o);
+        }
+      }
+    };
+    if (nkb > 1 && (nkb & 1)) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float t = sa[r];
+        sa[r] = sb[r];
+        sb[r] = t;
       }
     }
+    pass2(sa, sb);
     const float ltot = lsum + __shfl_xor(lsum, 32, 64);
     const float inv = 1.0f / ltot;
     if (qrow < L) {

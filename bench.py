@@ -318,7 +318,7 @@ def main() -> int:
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(records shard across GPUs without communication, see DESIGN.md)"}))
+                                   "(records are independent and shard across GPUs without communication)"}))
         return 2
     if a.serve:
         rates = [float(x) for x in a.serve.split(",")]

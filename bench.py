@@ -317,7 +317,7 @@ def main() -> int:
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
                                    "(records are independent and shard across GPUs without communication)"}))
         return 2
     if a.serve:

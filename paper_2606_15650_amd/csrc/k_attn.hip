@@ -5,21 +5,20 @@
 // the 1/sqrt(d) = 1/8 factor (applied exactly in the QKV GEMM epilogue).
 //
 // Two kernels.  BF16 operands (records of at most 512 keys): one workgroup
-// per (record, head) holds the record's whole K and V^T in LDS
-// (attn_resident_kernel, below).  FP32 operands: work item = (q-block of
-// 32*WAVES rows of one record, head); the block streams the record's keys in
-// tiles of 64, K rows and V^T staged in LDS.  In both, each wave owns 32
-// query rows and computes S^T = K Q^T with 32x32 MFMAs, so that every lane
-// holds the scores of one query row.  Records longer than one key block take
-// two passes over their keys: the first finds each row's exact maximum, the
-// second forms p = exp(s - max) once (FP32, base-2 exponentials), sums it in
-// FP32, rounds
-// it to the operand type and accumulates O^T += V^T P^T in FP32.  Rounding p
-// relative to the final maximum (not a running one) makes the rounded values
-// a function of the record alone, identical to the definition
-// softmax(s) = exp(s - max) / sum.  The MFMA k-index of P^T is a permutation
-// of the 32 keys of a block; V^T is read from LDS with the same permutation,
-// so the contraction is exact.
+// per (record, head) holds the record's whole K and V in LDS, V read back
+// transposed (attn_resident_kernel, below).  FP32 operands: work item =
+// (q-block of 32*WAVES rows of one record, head); the block streams the
+// record's keys in tiles of 64, K rows and V^T staged in LDS.  In both, each
+// wave owns 32 query rows and computes S^T = K Q^T with 32x32 MFMAs, so that
+// every lane holds the scores of one query row.  Records longer than one key
+// block take two passes over their keys: the first finds each row's exact
+// maximum, the second forms p = exp(s - max) once (FP32, base-2
+// exponentials), sums it in FP32, rounds it to the operand type and
+// accumulates O^T += V^T P^T in FP32.  Rounding p relative to the final
+// maximum (not a running one) makes the rounded values a function of the
+// record alone, identical to the definition softmax(s) = exp(s - max) / sum.
+// The MFMA k-index of P^T is a permutation of the 32 keys of a block; V^T is
+// read from LDS with the same permutation, so the contraction is exact.
 #include "kernels.hpp"
 
 namespace anon {
@@ -66,6 +65,34 @@ __device__ __forceinline__ bf16x8 vfrag(const bf16_t* vrow, int kb, int st, int 
   // kb*32 + 16*st + 8 + hh*4 + {0..3}
   const bf16x4 lo = *(const bf16x4*)(vrow + kb * 32 + 16 * st + hh * 4);
   const bf16x4 hi = *(const bf16x4*)(vrow + kb * 32 + 16 * st + 8 + hh * 4);
+  return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// V^T fragments of the record-resident kernel, read transposed from V kept
+// row-major in LDS (64 elements per row; in rows with bit 1 set, bit 5 of the
+// column is flipped).  ds_read_b64_tr_b16 works on groups of 16 lanes: each
+// lane names a 4-element chunk, and lane j of the group receives element
+// j % 4 of the chunks named by lanes j / 4 + 4k, k = 0..3.  Lane c of a group
+// names row (base + c / 4), logical columns db*32 + 16*(group parity) +
+// 4*(c % 4) (stored with the row's bit-5 flip), so
+// lane l receives V[base + k][db*32 + l % 32], k = 0..3: four consecutive
+// keys of its own V^T row.  base = kb*32 + 16*st + 8*q + 4*(l / 32) gives the
+// same key order as the P^T fragment (pfrag).  For a half-wave the 4 rows x
+// 32 columns then fall on 64 distinct banks.
+__device__ __forceinline__ int vtr_lane_offset(int lane, int db) {
+  const int c = lane & 15, g = (lane >> 4) & 1, hh = lane >> 5;
+  // rows base + c/4 with base a multiple of 4: bit 1 of the row is bit 3 of
+  // c; column bit 5 is db, flipped in those rows
+  const int col = 16 * g + 4 * (c & 3) + ((((c >> 3) & 1) ^ db) << 5);
+  return (hh * 4 + (c >> 2)) * D + col;
+}
+// vl: the lane's pointer for one 32-column half db (V + vtr_lane_offset)
+__device__ __forceinline__ bf16x8 vfrag_tr(const bf16_t* vl, int kb, int st) {
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+  typedef __attribute__((address_space(3))) bf16_t lds_bf16;
+  const bf16_t* p = vl + (kb * 32 + 16 * st) * D;
+  const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(lds_bf16*)p);
+  const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(lds_bf16*)(p + 8 * D));
   return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
@@ -241,11 +268,11 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
 // 32 lanes on distinct banks.  Records are binned by length so that RMAX and
 // the wave count follow the record (see kClassMax).
-// LDS bytes of a record-resident workgroup (V^T rows padded by 12 keys, K
-// rows by 8 elements) and the waves per SIMD that as many workgroups as fit
+// LDS bytes of a record-resident workgroup (V rows unpadded, K rows padded
+// by 8 elements) and the waves per SIMD that as many workgroups as fit
 // in the 160 KB of a CU's LDS bring; the register budget is held to that
 // occupancy.
-constexpr int resident_lds_bytes(int rmax) { return (D * (rmax + 12) + rmax * (D + 8)) * 2; }
+constexpr int resident_lds_bytes(int rmax) { return (rmax * D + rmax * (D + 8)) * 2; }
 constexpr int resident_waves_per_eu(int rmax, int waves) {
   return (163840 / resident_lds_bytes(rmax)) * waves / 4;
 }
@@ -259,7 +286,6 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
   typedef AMfma<bf16_t> MF;
   typedef bf16x8 frag;
   constexpr int KS = D + 8;       // K row stride (16 bytes of padding)
-  constexpr int VS = RMAX + 12;   // V^T row stride
   constexpr float LOG2E = 1.4426950408889634f;
   const int rb = blockIdx.x;
   if (rb >= *n_recs) return;
@@ -269,12 +295,14 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
   const int ld = 3 * hidden;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5;
 
-  // V^T first: its reads then sit below 64 KB, within reach of the
-  // instructions' immediate offsets
-  __shared__ __align__(16) bf16_t lds[D * VS + RMAX * KS];
+  // V first: its reads then sit below 64 KB, within reach of the
+  // instructions' immediate offsets.  V is kept row-major (key, d), 64
+  // elements per row, with bit 5 of the column flipped in rows whose bit 1 is
+  // set; the PV step reads it transposed (vfrag_tr).
+  __shared__ __align__(16) bf16_t lds[RMAX * D + RMAX * KS];
   static_assert(sizeof(lds) == resident_lds_bytes(RMAX), "LDS size");
-  bf16_t* const Vt = lds;
-  bf16_t* const Ks = lds + D * VS;
+  bf16_t* const Vs = lds;
+  bf16_t* const Ks = lds + RMAX * D;
 
   // A workgroup has one wave per 32 keys of the class bound, so every thread
   // stages exactly NSTG 16-byte chunks of K and of V, and every wave owns at
@@ -312,9 +340,7 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
     const int c = tid + i * NT, r = c >> 3, cc = c & 7;
     if (r < Lp) {
       *(intx4*)&Ks[r * KS + cc * 8] = kv[i];
-      const bf16_t* ve = (const bf16_t*)&vv[i];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) Vt[(cc * 8 + e) * VS + r] = ve[e];
+      *(intx4*)&Vs[r * D + (cc ^ (((r >> 1) & 1) << 2)) * 8] = vv[i];
     }
   }
   __syncthreads();
@@ -335,6 +361,8 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
           if (kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3) >= L) s[r] = -INFINITY;
       }
     };
+    const bf16_t* const vl0 = Vs + vtr_lane_offset(lane, 0);
+    const bf16_t* const vl1 = Vs + vtr_lane_offset(lane, 1);
     // pass 1: row maximum of the raw scores (the scale is positive, so the
     // maximum of the scaled scores is the scaled maximum)
     // Both passes are software-pipelined two blocks deep: the next block's
@@ -383,10 +411,7 @@ __global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) voi
       for (int stp = 0; stp < 2; ++stp) {
         const frag pb = pfrag<bf16_t>(s, stp);
 #pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const bf16_t* vrow = &Vt[(db * 32 + (lane & 31)) * VS + kb * 32];
-          acc[db] = MF::mma(vfrag(vrow, 0, stp, hh), pb, acc[db]);
-        }
+        for (int db = 0; db < 2; ++db) acc[db] = MF::mma(vfrag_tr(db ? vl1 : vl0, kb, stp), pb, acc[db]);
       }
     };
     // Pass 2 takes the blocks in the order nkb-2, nkb-1 (still in registers,

@@ -13,6 +13,8 @@ It is a plain, slow, direct statement of what the path computes, in float64:
   decoding (labels to byte ranges);
 * ``pseudonym``- HMAC-SHA256 slugs and the ``[TYPE_slug]`` substitution
   (Sec. II, stage 3);
+* ``recognizers`` - pattern recognizers beside the NER model (Sec. II,
+  stage 2) and the merge of overlapping detections;
 * ``pipeline`` - the three composed over a packed batch of records.
 
 It shares no code with the GPU path; the only common module is ``synth``

@@ -1,0 +1,98 @@
+"""Pins of the recognizer oracle: each rule against Python's regular-expression
+engine at every position of seeded random texts, hand-made overlap-resolution
+cases, and coverage of the generator's gold entities."""
+import random
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import recognizers as R
+
+# Pieces that assemble into matches, near-misses and boundary cases.
+PIECES = {
+    "URL": [b"http://", b"https://", b"htp://", b"http:/", b" ", b"x", b".", b"\n", b"_", b"a/b", b"\t"],
+    "EMAIL_ADDRESS": [b"ab", b"x1", b".", b"@", b"-", b"_", b"%", b"+", b" ", b"com", b"corp", b"c", b"a.b@",
+                      b"@h.co", b"..", b"9"],
+    "IP_ADDRESS": [b"1", b"25", b"255", b"256", b"0", b"01", b"199", b"2", b".", b".", b".", b" ", b"a", b"_",
+                   b"1.2.3.4", b"10.0.0."],
+    "MAC_ADDRESS": [b"0a", b"ff", b"1F", b":", b":", b"g", b" ", b"_", b"0a:1b:2c:3d:4e:5f", b"aa:bb:cc:dd:ee",
+                    b":00"],
+    "HASH": [b"0123456789abcdef", b"0123456789ABCDEF", b"abcd", b"01234567", b" ", b"g", b"_", b"."],
+    "CVE_ID": [b"CVE-", b"2021", b"-", b"12345", b"1", b"a", b" ", b"CVE-2021-1234567", b"_", b"cve-"],
+    "HOSTNAME": [b"a", b"b1", b"-", b".", b"corp", b"lan", b"local", b"net", b"org1", b" ", b"@", b"x.internal",
+                 b"/", b"Corp"],
+}
+
+
+@pytest.mark.parametrize("name", R.RECOGNIZERS)
+def test_rule_equals_regular_expression_at_every_position(name):
+    pat = re.compile(R.PATTERNS[name])
+    rule = R.MATCHERS[name]
+    rng = random.Random(R.RECOGNIZERS.index(name))
+    hits = 0
+    for _ in range(1500):
+        t = b"".join(rng.choice(PIECES[name]) for _ in range(rng.randint(1, 16)))
+        for p in range(len(t)):
+            m = pat.match(t, p)
+            want = m.end() if m else -1
+            assert rule(t, p) == want, (name, t, p)
+            hits += want >= 0
+    assert hits > 100, hits  # the texts do exercise matches
+
+
+def test_rules_on_written_examples():
+    cases = {
+        "IP_ADDRESS": [(b"host 10.0.0.255 up", 5, 15), (b"v1.2.3.4", 1, -1), (b"1.2.3.256", 0, -1),
+                       (b"01.2.3.4", 0, -1), (b"1.2.3.4.5", 0, 7), (b"1.2.3.4.5", 2, 9)],
+        "CVE_ID": [(b"(CVE-2021-44228)", 1, 15), (b"CVE-2021-123", 0, -1), (b"CVE-2021-12345678", 0, -1)],
+        "MAC_ADDRESS": [(b"mac 00:1a:2B:3c:4d:5e.", 4, 21), (b"00:1a:2b:3c:4d", 0, -1)],
+        "HASH": [(b"x " + b"a" * 40 + b" y", 2, 42), (b"a" * 41, 0, -1), (b"a" * 32 + b"g", 0, -1)],
+        "URL": [(b"see https://a.corp/kb now", 4, 21), (b"xhttps://a", 1, -1)],
+        "EMAIL_ADDRESS": [(b"to j.doe@mail.example.", 3, 21), (b"a@b.c1", 0, -1), (b"a@b.corp.x1", 0, 8)],
+        "HOSTNAME": [(b"at db-1.site.corp.", 3, 17), (b"a.b.org1", 0, -1), (b"a.corp.lan", 0, 10)],
+    }
+    for name, rows in cases.items():
+        for t, p, e in rows:
+            assert R.MATCHERS[name](t, p) == e, (name, t, p)
+
+
+def test_merge_unions_overlaps_and_keeps_touching_spans_apart():
+    # (begin, end, type, priority); NER spans have priority 0
+    assert R.merge([(0, 5, 1, 3), (5, 9, 2, 1)]) == [(1, 0, 5), (2, 5, 9)]          # touching: apart
+    assert R.merge([(0, 30, 6, 1), (8, 17, 2, 7)]) == [(6, 0, 30)]                   # URL holds a hostname
+    assert R.merge([(0, 6, 1, 0), (2, 12, 1, 3)]) == [(1, 0, 12)]                    # NER truncated an IP
+    assert R.merge([(0, 4, 3, 2), (0, 4, 5, 0)]) == [(5, 0, 4)]                      # tie: NER type wins
+    assert R.merge([(0, 4, 3, 2), (3, 8, 4, 5), (7, 20, 6, 1)]) == [(6, 0, 20)]      # chain, longest member
+    assert R.merge([(0, 4, 3, 4), (0, 4, 2, 2)]) == [(2, 0, 4)]                      # tie: lower recognizer
+    assert R.merge([]) == []
+
+
+def test_truncated_ner_span_is_extended_to_the_whole_entity():
+    t = b"Host: 100.111.20.23\n"
+    rt = R.recognizer_types(synth.TYPE_NAMES_17)
+    # an NER span covering only "100.111" would leak ".20.23"
+    got = R.resolve_record(t, [(1, 6, 13)], rt)
+    assert got == [(1, 6, 19)]
+
+
+def test_generator_gold_entities_are_covered():
+    """Every gold entity of a recognised type lies inside one resolved span
+    (recognizers alone, no NER spans).  Records are cut to an exact token
+    count, so an entity ending at the record's last byte may be truncated and
+    is left out."""
+    names = synth.TYPE_NAMES_17
+    rb = synth.generate_records(48, np.full(48, 300), len(names), 30522, 11)
+    rt = R.recognizer_types(names)
+    covered = total = 0
+    for i in range(rb.n_records):
+        t = rb.text[int(rb.cu_bytes[i]):int(rb.cu_bytes[i + 1])]
+        spans = R.resolve_record(t, [], rt)
+        for g in rb.gold_spans[rb.gold_spans[:, 0] == i]:
+            typ, b, e = int(g[1]), int(g[2]), int(g[3])
+            if names[typ - 1] == "PORT" or e == len(t):
+                continue  # a port is a bare number that no pattern names
+            total += 1
+            covered += any(sb <= b and e <= se for _, sb, se in spans)
+    assert total > 50 and covered == total, (covered, total)

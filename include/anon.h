@@ -56,7 +56,8 @@ enum {
   ANON_ERR_LABEL = 4,         /* label > 2*n_types (token treated as O)             */
   ANON_ERR_SPAN = 8,          /* span outside its record / overlapping (skipped)     */
   ANON_ERR_SPAN_CAP = 16,     /* more spans than span_cap (extra spans dropped)      */
-  ANON_ERR_OUT_CAP = 32       /* output larger than out_cap (output truncated)       */
+  ANON_ERR_OUT_CAP = 32,      /* output larger than out_cap (output truncated)       */
+  ANON_ERR_TEXT = 64          /* cu_bytes malformed or a record of >= 16 MiB (recognize_spans) */
 };
 
 /* Encoder shape.  head_dim = hidden / n_heads must be 64; n_labels = 2*types+1. */
@@ -195,6 +196,49 @@ anon_status anon_decode_workspace_size(int32_t T, int32_t B, size_t* bytes);
 anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, const int32_t* d_cu_seqlens, int32_t B,
                          int32_t T, int32_t n_types, anon_span* d_spans, int32_t span_cap, int32_t* d_cu_spans,
                          void* d_workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Pattern recognizers and overlap resolution (Sec. II stage 2 pairs the NER
+ * model with regular-expression recognizers; Sec. V shows the cost of
+ * overlapping detections that are not merged: truncated entities and extra
+ * pseudonyms)
+ * ------------------------------------------------------------------------
+ * Seven recognizers run over every byte of every record (W = [A-Za-z0-9_],
+ * LABEL = [A-Za-z0-9-], LOCAL = [A-Za-z0-9._%+-]), in this order:
+ *   0 URL        "http://" or "https://" at a word start, then >= 1 non-space bytes
+ *   1 EMAIL      maximal LOCAL run, '@', >= 1 "label." groups, then an all-letter
+ *                top label of >= 2 bytes not followed by LABEL (longest domain)
+ *   2 IPV4       four dot-separated octets 0..255, no leading zeros, word-bounded
+ *   3 MAC        six hex pairs separated by ':', word-bounded
+ *   4 HASH       a hex run of exactly 32, 40 or 64 bytes, word-bounded
+ *   5 CVE        "CVE-" + 4 digits + '-' + 4..7 digits, word-bounded
+ *   6 HOSTNAME   a dotted LABEL run not preceded by LABEL or '.', ending at a label
+ *                equal to corp, lan, intra, net, org, local, example or internal
+ *                and not followed by LABEL (longest)
+ * Every start byte where a rule matches gives a candidate span.  The NER spans
+ * and the candidates that share a byte are merged into their union
+ * (transitively; spans that only touch stay apart); the union takes the type
+ * of its longest member, then NER before recognizers (in the order above),
+ * then the leftmost member.  The output feeds pseudonymize().
+ *   d_text, d_cu_bytes  record bytes back to back, int64 offsets [B+1]
+ *                       (cu_bytes[0] = 0, cu_bytes[B] = n_bytes, records below
+ *                       16 MiB; otherwise ANON_ERR_TEXT is raised)
+ *   n_bytes      host copy of cu_bytes[B] (sizes the launch), below 2^31 - 2
+ *   h_rec_types  int32 [7] host: type index (1..n_types) each recognizer emits,
+ *                0 switches it off
+ *   d_ner_spans, d_ner_cu, ner_cap  decode_spans() output and its capacity
+ *                (ner_cap = 0: recognizers alone; spans outside their record
+ *                raise ANON_ERR_SPAN and are ignored)
+ *   d_spans      out: up to span_cap merged spans, record-major, in byte order
+ *   d_cu_spans   int32 [B+1] out: record b owns [cu_spans[b], cu_spans[b+1]);
+ *                cu_spans[B] is the total even when it exceeds span_cap
+ *                (then ANON_ERR_SPAN_CAP is raised)
+ *   d_workspace  >= anon_recognize_workspace_size(n_bytes, B) bytes. */
+anon_status anon_recognize_workspace_size(int64_t n_bytes, int32_t B, size_t* bytes);
+anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, int32_t B, int64_t n_bytes,
+                            const int32_t* h_rec_types, int32_t n_types, const anon_span* d_ner_spans,
+                            const int32_t* d_ner_cu, int32_t ner_cap, anon_span* d_spans, int32_t span_cap,
+                            int32_t* d_cu_spans, void* d_workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Pseudonyms (Sec. II stage 3)

@@ -20,7 +20,7 @@ ANON_OK, ANON_PENDING = 0, 1
 STATUS = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY",
           -5: "EBUSY", -6: "ENOTFOUND", -7: "EDATA"}
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2}
-ERR_TOKEN_ID, ERR_SEQLENS, ERR_LABEL, ERR_SPAN, ERR_SPAN_CAP, ERR_OUT_CAP = 1, 2, 4, 8, 16, 32
+ERR_TOKEN_ID, ERR_SEQLENS, ERR_LABEL, ERR_SPAN, ERR_SPAN_CAP, ERR_OUT_CAP, ERR_TEXT = 1, 2, 4, 8, 16, 32, 64
 KCLASS = {"qkv": 0, "attn": 1, "oproj": 2, "ffn1": 3, "ffn2": 4, "ln": 5, "embed": 6, "cls": 7}
 
 
@@ -75,6 +75,8 @@ _SIGS = {
     "ner_forward_windowed": ([vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
     "decode_spans": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+    "anon_recognize_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
+    "recognize_spans": ([vp, vp, i32, i64, C.POINTER(i32), i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
     "anon_pcache_create": ([vp, sz, i32, C.POINTER(C.c_char_p), i32, i64, i32, C.POINTER(vp)], i32),
     "anon_pcache_free": ([vp], None),
     "anon_pcache_clear": ([vp, vp], i32),
@@ -245,6 +247,31 @@ def decode_spans(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int
     _check("decode_spans", lib().decode_spans(ptr(d_labels), ptr(d_tok_off), ptr(d_cu_seqlens), B, T, n_types,
                                               ptr(d_spans), span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,
                                               stream_handle(stream)))
+
+
+# Recognizer order of recognize_spans (the type each emits is chosen per call).
+RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME"]
+
+
+def recognizer_types(type_names) -> list[int]:
+    """Type index (1-based) each recognizer emits for a model's type names; 0 = off."""
+    names = list(type_names)
+    return [names.index(r) + 1 if r in names else 0 for r in RECOGNIZERS]
+
+
+def recognize_workspace_size(n_bytes: int, B: int) -> int:
+    n = sz()
+    _check("anon_recognize_workspace_size", lib().anon_recognize_workspace_size(n_bytes, B, C.byref(n)))
+    return n.value
+
+
+def recognize_spans(d_text, d_cu_bytes, B: int, n_bytes: int, rec_types, n_types: int, d_ner_spans, d_ner_cu,
+                    ner_cap: int, d_spans, span_cap: int, d_cu_spans, d_workspace, ws_bytes: int, stream=None):
+    rt = (i32 * 7)(*[int(x) for x in rec_types])
+    _check("recognize_spans", lib().recognize_spans(ptr(d_text), ptr(d_cu_bytes), B, n_bytes, rt, n_types,
+                                                    ptr(d_ner_spans), ptr(d_ner_cu), ner_cap, ptr(d_spans),
+                                                    span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,
+                                                    stream_handle(stream)))
 
 
 # ------------------------------------------------------------- pseudonyms --

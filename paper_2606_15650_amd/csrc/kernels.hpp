@@ -104,6 +104,22 @@ void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 // n elements of type t, uniform in [-1, 1) (benchmark and tuning operands)
 void launch_fill_random(void* p, ElemType t, int64_t n, uint32_t seed, hipStream_t s);
 
+// ---- pattern recognizers and overlap resolution ---------------------------
+struct RecogBuffers {
+  int *delta, *starts, *cover, *fstart, *fend, *sstart, *send;
+  unsigned long long *key, *run_key;
+  uint8_t* ner_type;
+  int64_t *run_begin, *run_end;
+  void* temp;
+};
+RecogBuffers recog_layout(int64_t n_bytes, Carver& k);
+size_t recog_workspace_bytes(int64_t n_bytes);
+// rec_types: type index of each of the 7 recognizers (0 = off).  ner/ner_cu
+// may be null (no NER spans).
+void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64_t n_bytes, const int rec_types[7],
+                      const anon_span* ner, const int* ner_cu, int ner_cap, int n_types, const RecogBuffers& w,
+                      anon_span* out, int cap, int* cu_spans, uint32_t* err, hipStream_t s);
+
 // Shape of a created model (the struct itself is private to the runtime).
 const anon_model_config* model_config(const anon_model* m);
 

@@ -807,6 +807,40 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
   return ANON_OK;
 }
 
+anon_status anon_recognize_workspace_size(int64_t n_bytes, int32_t B, size_t* bytes) {
+  if (!bytes || n_bytes < 0 || B < 0) return set_error(ANON_EINVAL, "bad arguments");
+  *bytes = recog_workspace_bytes(n_bytes);
+  return ANON_OK;
+}
+
+anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, int32_t B, int64_t n_bytes,
+                            const int32_t* h_rec_types, int32_t n_types, const anon_span* d_ner_spans,
+                            const int32_t* d_ner_cu, int32_t ner_cap, anon_span* d_spans, int32_t span_cap,
+                            int32_t* d_cu_spans, void* d_workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (B < 0 || n_bytes < 0 || span_cap < 0 || ner_cap < 0) return set_error(ANON_EINVAL, "negative size");
+  if (B == 0 && n_bytes != 0) return set_error(ANON_EINVAL, "n_bytes > 0 with no records");
+  if (n_bytes >= (int64_t(1) << 31) - 2) return set_error(ANON_EINVAL, "n_bytes must be below 2^31 - 2");
+  if (n_types < 1 || n_types > 127) return set_error(ANON_EINVAL, "n_types must be in [1, 127]");
+  if (!h_rec_types) return set_error(ANON_EINVAL, "rec_types is NULL");
+  int rt[7];
+  for (int k = 0; k < 7; ++k) {
+    rt[k] = h_rec_types[k];
+    if (rt[k] < 0 || rt[k] > n_types) return set_error(ANON_EINVAL, "recognizer type outside [0, n_types]");
+  }
+  if (!d_cu_spans || !d_cu_bytes) return set_error(ANON_EINVAL, "cu arrays are NULL");
+  if (n_bytes > 0 && !d_text) return set_error(ANON_EINVAL, "text is NULL");
+  if (span_cap > 0 && !d_spans) return set_error(ANON_EINVAL, "spans is NULL");
+  if (ner_cap > 0 && (!d_ner_spans || !d_ner_cu)) return set_error(ANON_EINVAL, "NER spans are NULL");
+  Carver k(d_workspace, ws_bytes);
+  const RecogBuffers w = recog_layout(n_bytes, k);
+  if (!d_workspace || !k.ok()) return set_error(ANON_ECAPACITY, "workspace too small");
+  launch_recognize(d_text, d_cu_bytes, B, n_bytes, rt, d_ner_spans, d_ner_cu, ner_cap, n_types, w, d_spans,
+                   span_cap, d_cu_spans, error_word_ptr(), (hipStream_t)stream);
+  ANON_HIP_CHECK(hipGetLastError());
+  return ANON_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------- pseudonyms ----

@@ -91,6 +91,22 @@ class Pipeline:
                          stream)
         return spans, cu_spans, cap
 
+    def recognize(self, db: DeviceBatch, ner_spans=None, ner_cu=None, ner_cap: int = 0, span_cap: int | None = None,
+                  stream=None):
+        """Recognizer candidates merged with the NER spans (if given) into whole-entity spans.
+
+        The unions are disjoint and each holds an NER span or a recognizer
+        match of at least 5 bytes, so ner_cap + n_bytes / 5 + 1 of them always
+        fit."""
+        cap = (ner_cap + db.n_bytes // 5 + 1) if span_cap is None else span_cap
+        spans = torch.empty((max(cap, 1), 3), dtype=torch.int64, device=self.device)
+        cu_spans = torch.empty(db.B + 1, dtype=torch.int32, device=self.device)
+        ws = self._buf("rx", api.recognize_workspace_size(db.n_bytes, db.B))
+        rt = api.recognizer_types(self.cache.type_names)
+        api.recognize_spans(db.text, db.cu_bytes, db.B, db.n_bytes, rt, self.n_types, ner_spans, ner_cu, ner_cap,
+                            spans, cap, cu_spans, ws, ws.numel(), stream)
+        return spans, cu_spans, cap
+
     def out_capacity(self, db: DeviceBatch, span_cap: int) -> int:
         longest = max(len(n) for n in self.cache.type_names)
         return db.n_bytes + span_cap * (2 + longest + 1 + self.cache.slug) + 1
@@ -105,10 +121,14 @@ class Pipeline:
                          ws.numel(), stream)
         return out, cu_out
 
-    def step(self, db: DeviceBatch, window: int = 0, stride: int = 0, stream=None):
-        """One pass of the whole path over a resident batch (all on one stream)."""
+    def step(self, db: DeviceBatch, window: int = 0, stride: int = 0, recognizers: bool = False, stream=None):
+        """One pass of the whole path over a resident batch (all on one stream);
+        with recognizers, the NER spans are merged with the pattern recognizers'
+        before substitution."""
         labels, _, _ = self.ner(db, logits=False, margin=False, window=window, stride=stride, stream=stream)
         spans, cu_spans, cap = self.spans(db, labels, stream=stream)
+        if recognizers:
+            spans, cu_spans, cap = self.recognize(db, spans, cu_spans, cap, stream=stream)
         out, cu_out = self.pseudonymize(db, spans, cu_spans, cap, stream=stream)
         return labels, spans, cu_spans, out, cu_out
 

@@ -1,0 +1,200 @@
+"""GPU parity of the pattern recognizers and overlap resolution (recognize_spans)
+against the oracle: spans bit-exact, and substituted bytes bit-exact through the
+whole path."""
+import random
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pseudonym as ops, recognizers as R, spans as ospans
+from synth.configs import TINY
+from synth.records import RecordBatch
+from tests.gpu_common import make_cache, make_model, say
+from tests.test_oracle_recognizers import PIECES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _text_batch(records: list[bytes], type_names) -> RecordBatch:
+    cu = np.concatenate([[0], np.cumsum([len(r) for r in records])]).astype(np.int64)
+    B = len(records)
+    return RecordBatch(b"".join(records), cu, np.zeros(0, np.int32), np.zeros((0, 2), np.int32),
+                       np.zeros(B + 1, np.int32), np.zeros(0, np.uint8), np.zeros((0, 4), np.int64),
+                       list(type_names))
+
+
+def _pipeline(cache, n_types):
+    import torch
+    from paper_2606_15650_amd.pipeline import Pipeline
+    pl = Pipeline.__new__(Pipeline)
+    pl.cache, pl.device, pl._ws, pl.n_types = cache, torch.device("cuda:0"), {}, n_types
+    return pl
+
+
+def _ner_device(spans: np.ndarray, B: int):
+    import torch
+    n = len(spans)
+    raw = np.zeros((max(n, 1), 3), np.int64)
+    if n:
+        raw[:n, 0] = (spans[:, 0] & 0xFFFFFFFF) | (spans[:, 1] << 32)
+        raw[:n, 1] = spans[:, 2]
+        raw[:n, 2] = spans[:, 3]
+    counts = np.bincount(spans[:, 0], minlength=B) if n else np.zeros(B, np.int64)
+    cu = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return torch.from_numpy(raw).cuda(), torch.from_numpy(cu).cuda(), n
+
+
+def _recognize_gpu(rb, cache, ner: np.ndarray | None = None, span_cap=None):
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, spans_to_numpy
+    db = DeviceBatch(rb)
+    pl = _pipeline(cache, len(rb.type_names))
+    if ner is None:
+        spans, cu, cap = pl.recognize(db, span_cap=span_cap)
+    else:
+        d_sp, d_cu, n = _ner_device(ner, rb.n_records)
+        spans, cu, cap = pl.recognize(db, d_sp, d_cu, n, span_cap=span_cap)
+    torch.cuda.synchronize()
+    cu_h = cu.cpu().numpy().astype(np.int64)
+    arr = spans_to_numpy(spans, int(min(cu_h[-1], cap)))
+    return cu_h, arr
+
+
+def _per_record(cu_h, arr, B):
+    out = []
+    for b in range(B):
+        rows = arr[cu_h[b]:cu_h[b + 1]]
+        assert (rows[:, 0] == b).all()
+        out.append([(int(t), int(s), int(e)) for _, t, s, e in rows])
+    return out
+
+
+def _ner_lists(spans: np.ndarray, B: int):
+    out = [[] for _ in range(B)]
+    for r, t, b, e in spans.tolist():
+        out[r].append((t, b, e))
+    return out
+
+
+def _adversarial_records(n: int, seed: int) -> list[bytes]:
+    rng = random.Random(seed)
+    allp = [p for ps in PIECES.values() for p in ps]
+    recs = []
+    for i in range(n):
+        if i % 37 == 0:
+            recs.append(b"")  # empty record
+            continue
+        name = rng.choice(list(PIECES))
+        pool = PIECES[name] if rng.random() < 0.7 else allp
+        recs.append(b"".join(rng.choice(pool) for _ in range(rng.randint(1, 40))))
+    return recs
+
+
+def test_recognizers_alone_on_adversarial_texts(torch_dev):
+    names = synth.TYPE_NAMES_17
+    rb = _text_batch(_adversarial_records(600, 5), names)
+    cache = make_cache(names)
+    say(f"[recognize] {rb.n_records} adversarial records, {len(rb.text)} bytes")
+    cu_h, arr = _recognize_gpu(rb, cache)
+    got = _per_record(cu_h, arr, rb.n_records)
+    want = R.resolve_batch(rb.text, rb.cu_bytes, [[] for _ in range(rb.n_records)], names)
+    assert sum(map(len, want)) > 300
+    assert got == want
+
+
+def test_recognizers_merge_truncated_ner_spans(torch_dev):
+    """Gold entities stand in for NER spans; a third of them are cut short
+    (as an NER boundary error would), so the recognizers must extend them."""
+    names = synth.TYPE_NAMES_17
+    rb = synth.generate_records(300, ("lognormal", 5.2, 0.6, 16, 512), len(names), 30522, 41)
+    ner = rb.gold_spans.astype(np.int64).copy()
+    cut = np.arange(len(ner)) % 3 == 0
+    ner[cut, 3] = np.maximum(ner[cut, 2] + 1, (ner[cut, 2] + ner[cut, 3]) // 2)
+    cache = make_cache(names)
+    say(f"[recognize] {rb.n_records} records with {len(ner)} NER spans ({cut.sum()} truncated)")
+    cu_h, arr = _recognize_gpu(rb, cache, ner)
+    got = _per_record(cu_h, arr, rb.n_records)
+    want = R.resolve_batch(rb.text, rb.cu_bytes, _ner_lists(ner, rb.n_records), names)
+    assert got == want
+
+
+def test_full_path_with_recognizers_matches_oracle(torch_dev):
+    """Tiny model: GPU labels -> spans -> recognizers (URL, MAC, HASH off: the
+    4-type model has no such types) -> substitution, against the oracle on the
+    same labels."""
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list
+    W, m = make_model(TINY, "fp32", 0)
+    rb = synth.generate_records(64, ("uniform", 16, 128), (TINY.n_labels - 1) // 2, TINY.vocab, 0)
+    cache = make_cache(rb.type_names)
+    pl = Pipeline(m, cache)
+    db = DeviceBatch(rb)
+    say("[recognize] tiny full path with recognizers")
+    labels, spans, cu_spans, out, cu_out = pl.step(db, recognizers=True)
+    torch.cuda.synchronize()
+    got = outputs_to_list(out, cu_out)
+    lab = labels[:db.T].cpu().numpy()
+    key = synth.make_key(0)
+    n_types = len(rb.type_names)
+    rt = R.recognizer_types(rb.type_names)
+    assert rt[0] == rt[3] == rt[4] == 0
+    want = []
+    for b in range(rb.n_records):
+        a, e = int(rb.cu_seqlens[b]), int(rb.cu_seqlens[b + 1])
+        t = rb.text[int(rb.cu_bytes[b]):int(rb.cu_bytes[b + 1])]
+        ner = ospans.bio_decode_record(lab[a:e], rb.tok_off[a:e], n_types)
+        merged = R.resolve_record(t, ner, rt)
+        want.append(ops.substitute(t, merged, rb.type_names, key, cache.slug))
+    assert got == want
+
+
+def test_capacity_bad_spans_and_empty_batch(torch_dev):
+    from paper_2606_15650_amd import api
+    names = synth.TYPE_NAMES_17
+    rb = _text_batch([b"ip 10.0.0.1 and 10.0.0.2", b"", b"CVE-2021-44228 x 00:11:22:33:44:55"], names)
+    cache = make_cache(names)
+    want = R.resolve_batch(rb.text, rb.cu_bytes, [[], [], []], names)
+    total = sum(map(len, want))
+    assert total == 4
+    api.device_errors(0, clear=True)
+    cu_h, arr = _recognize_gpu(rb, cache, span_cap=2)
+    assert cu_h.tolist() == [0, 2, 2, 4]
+    assert [tuple(x) for x in arr.tolist()] == [(0, t, b, e) for t, b, e in want[0]]
+    assert api.device_errors(0, clear=True) & api.ERR_SPAN_CAP
+    # an NER span past its record's end is ignored and flagged
+    bad = np.array([[0, 1, 3, 999]], np.int64)
+    cu_h, arr = _recognize_gpu(rb, cache, bad)
+    assert _per_record(cu_h, arr, 3) == want
+    assert api.device_errors(0, clear=True) & api.ERR_SPAN
+    # malformed cu_bytes (not ending at n_bytes) is flagged, reads stay in the text
+    rb2 = _text_batch([b"1.2.3.4", b"x"], names)
+    rb2.cu_bytes = np.array([0, 7, 5], np.int64)
+    _recognize_gpu(rb2, cache)
+    assert api.device_errors(0, clear=True) & api.ERR_TEXT
+    # no records
+    cu_h, arr = _recognize_gpu(_text_batch([], names), cache)
+    assert cu_h.tolist() == [0] and len(arr) == 0
+
+
+def test_base_batch_sampled_records(torch_dev):
+    """The bench's 4096-record batch, recognizers alone, in one launch; sampled
+    records against the oracle."""
+    wl = synth.workload("base_bf16")
+    cfg = wl.model
+    rb = synth.generate_records(wl.n_records, wl.lengths, (cfg.n_labels - 1) // 2, cfg.vocab, wl.seed)
+    cache = make_cache(rb.type_names)
+    say(f"[recognize] base batch {rb.n_records} records, {len(rb.text)} bytes")
+    cu_h, arr = _recognize_gpu(rb, cache)
+    got = _per_record(cu_h, arr, rb.n_records)
+    rt = R.recognizer_types(rb.type_names)
+    for b in np.random.default_rng(3).choice(rb.n_records, 120, replace=False).tolist() + [rb.n_records - 1]:
+        t = rb.text[int(rb.cu_bytes[b]):int(rb.cu_bytes[b + 1])]
+        assert got[b] == R.resolve_record(t, [], rt), b

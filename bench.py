@@ -315,6 +315,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
+    ap.add_argument("--no-recognizers", action="store_true",
+                    help="skip the timing of the path with the pattern recognizers merged in")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
@@ -393,12 +395,39 @@ def main() -> int:
                 kern[k] = api.prof_read(k)
                 api.prof_enable(k, False)
         st = cache.stats()
-        n_spans = None
+        rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if recog else None
         model.close()
         cache.close()
-        return wall, per, kern, st, tiles
+        return wall, per, kern, st, tiles, rx
 
-    wall, per, kern, cstats, tiles = run_path(wl.precision, a.steps, a.warmup, prof=True)
+    def recognizer_timing(pl, db, stream, steps: int) -> dict:
+        """The same step with the pattern recognizers merged into the NER spans,
+        and recognize_spans alone (HIP events on its stream) over the batch text."""
+        pl.step(db, recognizers=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pl.step(db, recognizers=True)
+        torch.cuda.synchronize()
+        wall_r = time.perf_counter() - t0
+        labels, _, _ = pl.ner(db, logits=False, margin=False, stream=stream)
+        spans, cu_spans, cap = pl.spans(db, labels, stream=stream)
+        reps = 10
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+        for i in range(reps):
+            ev[2 * i].record(stream)
+            _, cu_r, _ = pl.recognize(db, spans, cu_spans, cap, stream=stream)
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+        return {"value": T * steps / wall_r, "unit": "tokens/s", "ms_per_step": wall_r / steps * 1e3,
+                "recognize_ms": ms, "text_bytes": db.n_bytes, "text_GBps": db.n_bytes / (ms * 1e-3) / 1e9,
+                "ner_spans": int(cu_spans[-1].item()), "merged_spans": int(cu_r[-1].item()),
+                "recognizers": api.RECOGNIZERS}
+
+    recog = not a.no_recognizers
+    wall, per, kern, cstats, tiles, rx = run_path(wl.precision, a.steps, a.warmup, prof=True)
+    recog = False
     tokens_per_s = T * a.steps / wall
     # dominant kernel class (largest total time) against its roofline
     gemm_tok = gemm_flops_per_token(cfg)
@@ -453,8 +482,10 @@ def main() -> int:
         "gemm_tiles": dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles)),
         "input_gen_s": gen_s,
     }
+    if rx is not None:
+        out["with_recognizers"] = rx
     if not a.no_fp32 and wl.precision != "fp32":
-        w32, per32, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
+        w32, per32, _, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
         tps32 = T * max(2, a.steps // 4) / w32
         out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
     if not a.no_cpu:

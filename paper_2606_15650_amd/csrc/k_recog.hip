@@ -45,17 +45,21 @@ __device__ __forceinline__ bool is_hex(uint8_t c) {
 }
 __device__ __forceinline__ bool is_space(uint8_t c) { return c == ' ' || (c >= '\t' && c <= '\r'); }
 
-// One record's bytes t[lo, hi); positions are absolute.
+// One record's bytes [lo, hi) of the text; positions are absolute.  Bytes
+// inside the workgroup's staged window [wlo, whi) are read from LDS, the rest
+// (long runs past the window) from global memory.
 struct Rec {
   const uint8_t* t;
   int64_t lo, hi;
-  __device__ uint8_t at(int64_t i) const { return t[i]; }
-  __device__ bool word_start(int64_t p) const { return is_word(t[p]) && (p == lo || !is_word(t[p - 1])); }
-  __device__ bool word_end(int64_t q) const { return q == hi || !is_word(t[q]); }
+  const uint8_t* win;
+  int64_t wlo, whi;
+  __device__ uint8_t at(int64_t i) const { return (i >= wlo && i < whi) ? win[i - wlo] : t[i]; }
+  __device__ bool word_start(int64_t p) const { return is_word(at(p)) && (p == lo || !is_word(at(p - 1))); }
+  __device__ bool word_end(int64_t q) const { return q == hi || !is_word(at(q)); }
   __device__ bool has(int64_t p, const char* s, int n) const {
     if (p + n > hi) return false;
     for (int i = 0; i < n; ++i)
-      if (t[p + i] != (uint8_t)s[i]) return false;
+      if (at(p + i) != (uint8_t)s[i]) return false;
     return true;
   }
 };
@@ -67,15 +71,15 @@ __device__ int64_t match_url(const Rec& r, int64_t p) {
   else if (r.has(p, "http://", 7)) q = p + 7;
   else return -1;
   int64_t e = q;
-  while (e < r.hi && !is_space(r.t[e])) ++e;
+  while (e < r.hi && !is_space(r.at(e))) ++e;
   return e > q ? e : -1;
 }
 
 // An all-letter label of >= 2 bytes at s, not followed by a LABEL byte.
 __device__ int64_t top_letters(const Rec& r, int64_t s) {
   int64_t e = s;
-  while (e < r.hi && is_letter(r.t[e])) ++e;
-  return (e - s >= 2 && (e == r.hi || !is_label(r.t[e]))) ? e : -1;
+  while (e < r.hi && is_letter(r.at(e))) ++e;
+  return (e - s >= 2 && (e == r.hi || !is_label(r.at(e)))) ? e : -1;
 }
 
 // One of the eight top labels at s, not followed by a LABEL byte.
@@ -83,7 +87,7 @@ __device__ int64_t top_listed(const Rec& r, int64_t s) {
   const char* const tops[8] = {"corp", "lan", "intra", "net", "org", "local", "example", "internal"};
   const int lens[8] = {4, 3, 5, 3, 3, 5, 7, 8};
   for (int k = 0; k < 8; ++k)
-    if (r.has(s, tops[k], lens[k]) && (s + lens[k] == r.hi || !is_label(r.t[s + lens[k]]))) return s + lens[k];
+    if (r.has(s, tops[k], lens[k]) && (s + lens[k] == r.hi || !is_label(r.at(s + lens[k])))) return s + lens[k];
   return -1;
 }
 
@@ -95,8 +99,8 @@ __device__ int64_t dotted_domain(const Rec& r, int64_t i) {
   int groups = 0;
   while (true) {
     int64_t j = i;
-    while (j < r.hi && is_label(r.t[j])) ++j;
-    const bool group = j > i && j < r.hi && r.t[j] == '.';
+    while (j < r.hi && is_label(r.at(j))) ++j;
+    const bool group = j > i && j < r.hi && r.at(j) == '.';
     if (groups >= 1) {
       const int64_t e = LISTED ? top_listed(r, i) : top_letters(r, i);
       if (e >= 0) best = e;
@@ -108,15 +112,15 @@ __device__ int64_t dotted_domain(const Rec& r, int64_t i) {
 }
 
 __device__ int64_t match_email(const Rec& r, int64_t p) {
-  if (!is_local(r.t[p]) || (p > r.lo && is_local(r.t[p - 1]))) return -1;
+  if (!is_local(r.at(p)) || (p > r.lo && is_local(r.at(p - 1)))) return -1;
   int64_t q = p;
-  while (q < r.hi && is_local(r.t[q])) ++q;
-  if (q == r.hi || r.t[q] != '@') return -1;
+  while (q < r.hi && is_local(r.at(q))) ++q;
+  if (q == r.hi || r.at(q) != '@') return -1;
   return dotted_domain<false>(r, q + 1);
 }
 
 __device__ int64_t match_hostname(const Rec& r, int64_t p) {
-  if (!is_label(r.t[p]) || (p > r.lo && (is_label(r.t[p - 1]) || r.t[p - 1] == '.'))) return -1;
+  if (!is_label(r.at(p)) || (p > r.lo && (is_label(r.at(p - 1)) || r.at(p - 1) == '.'))) return -1;
   return dotted_domain<true>(r, p);
 }
 
@@ -124,20 +128,20 @@ __device__ int64_t match_hostname(const Rec& r, int64_t p) {
 __device__ int64_t octet(const Rec& r, int64_t i) {
   int64_t e = i;
   int v = 0;
-  while (e < r.hi && is_digit(r.t[e]) && e - i < 4) v = v * 10 + (r.t[e++] - '0');
+  while (e < r.hi && is_digit(r.at(e)) && e - i < 4) v = v * 10 + (r.at(e++) - '0');
   const int64_t c = e - i;
-  if (c < 1 || c > 3 || (c > 1 && r.t[i] == '0') || v > 255) return -1;
+  if (c < 1 || c > 3 || (c > 1 && r.at(i) == '0') || v > 255) return -1;
   return e;
 }
 
 __device__ int64_t match_ipv4(const Rec& r, int64_t p) {
-  if (!is_digit(r.t[p]) || !r.word_start(p)) return -1;
+  if (!is_digit(r.at(p)) || !r.word_start(p)) return -1;
   int64_t i = p;
   for (int k = 0; k < 4; ++k) {
     const int64_t e = octet(r, i);
     if (e < 0) return -1;
     if (k == 3) return r.word_end(e) ? e : -1;
-    if (e == r.hi || r.t[e] != '.') return -1;
+    if (e == r.hi || r.at(e) != '.') return -1;
     i = e + 1;
   }
   return -1;
@@ -146,16 +150,16 @@ __device__ int64_t match_ipv4(const Rec& r, int64_t p) {
 __device__ int64_t match_mac(const Rec& r, int64_t p) {
   if (!r.word_start(p) || p + 17 > r.hi) return -1;
   for (int k = 0; k < 17; ++k) {
-    const uint8_t c = r.t[p + k];
+    const uint8_t c = r.at(p + k);
     if (k % 3 == 2 ? c != ':' : !is_hex(c)) return -1;
   }
   return r.word_end(p + 17) ? p + 17 : -1;
 }
 
 __device__ int64_t match_hash(const Rec& r, int64_t p) {
-  if (!is_hex(r.t[p]) || !r.word_start(p)) return -1;
+  if (!is_hex(r.at(p)) || !r.word_start(p)) return -1;
   int64_t e = p;
-  while (e < r.hi && is_hex(r.t[e]) && e - p < 65) ++e;
+  while (e < r.hi && is_hex(r.at(e)) && e - p < 65) ++e;
   const int64_t c = e - p;
   return ((c == 32 || c == 40 || c == 64) && r.word_end(e)) ? e : -1;
 }
@@ -163,15 +167,17 @@ __device__ int64_t match_hash(const Rec& r, int64_t p) {
 __device__ int64_t match_cve(const Rec& r, int64_t p) {
   if (!r.word_start(p) || p + 9 > r.hi || !r.has(p, "CVE-", 4)) return -1;
   for (int k = 0; k < 4; ++k)
-    if (!is_digit(r.t[p + 4 + k])) return -1;
-  if (r.t[p + 8] != '-') return -1;
+    if (!is_digit(r.at(p + 4 + k))) return -1;
+  if (r.at(p + 8) != '-') return -1;
   int64_t e = p + 9;
-  while (e < r.hi && is_digit(r.t[e]) && e - (p + 9) < 8) ++e;
+  while (e < r.hi && is_digit(r.at(e)) && e - (p + 9) < 8) ++e;
   const int64_t c = e - (p + 9);
   return (c >= 4 && c <= 7 && r.word_end(e)) ? e : -1;
 }
 
 constexpr int kRecognizers = 7;
+constexpr int kPerBlock = 256;                 // start bytes per match workgroup (one per thread)
+constexpr int kWin = 1 + kPerBlock + 1024;      // staged bytes (1 before, 1024 ahead)
 struct RecTypes {
   int t[kRecognizers];  // type index per recognizer, 0 = off
 };
@@ -224,38 +230,52 @@ __global__ __launch_bounds__(256) void rx_match_kernel(const uint8_t* __restrict
                                                        const int64_t* __restrict__ cu, int B, int64_t n,
                                                        RecTypes rt, int* delta, int* starts,
                                                        unsigned long long* key, uint32_t* err) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
-  const int b = find_record(cu, B, p);
-  int64_t lo, hi;
-  record_bounds(cu, b, n, lo, hi);
-  if (p < lo || p >= hi) return;  // only with a malformed cu_bytes
-  const Rec r{text, lo, hi};
-  int count = 0;
-  unsigned long long best = 0;
+  // the workgroup's kPerBlock start bytes, the byte before them and 1024
+  // bytes of lookahead, staged in LDS (coalesced loads)
+  __shared__ uint8_t win[kWin];
+  const int64_t p0 = (int64_t)blockIdx.x * kPerBlock;
+  const int64_t wlo = p0 > 0 ? p0 - 1 : 0;
+  const int64_t whi = min(wlo + kWin, n);
+  for (int64_t i = wlo + threadIdx.x; i < whi; i += 256) win[i - wlo] = text[i];
+  __syncthreads();
+  // positions p0 + tid + 256 j (one when kPerBlock = 256; more per thread
+  // measured slower): one record search, then a forward walk
+  int b = -1;
+  for (int j = 0; j < kPerBlock / 256; ++j) {
+    const int64_t p = p0 + threadIdx.x + 256 * j;
+    if (p >= n) return;
+    if (b < 0) b = find_record(cu, B, p);
+    while (b + 1 < B && cu[b + 1] <= p) ++b;
+    int64_t lo, hi;
+    record_bounds(cu, b, n, lo, hi);
+    if (p < lo || p >= hi) continue;  // only with a malformed cu_bytes
+    const Rec r{text, lo, hi, win, wlo, whi};
+    int count = 0;
+    unsigned long long best = 0;
 #pragma unroll
-  for (int k = 0; k < kRecognizers; ++k) {
-    if (rt.t[k] == 0) continue;
-    int64_t e;
-    switch (k) {
-      case 0: e = match_url(r, p); break;
-      case 1: e = match_email(r, p); break;
-      case 2: e = match_ipv4(r, p); break;
-      case 3: e = match_mac(r, p); break;
-      case 4: e = match_hash(r, p); break;
-      case 5: e = match_cve(r, p); break;
-      default: e = match_hostname(r, p); break;
+    for (int k = 0; k < kRecognizers; ++k) {
+      if (rt.t[k] == 0) continue;
+      int64_t e;
+      switch (k) {
+        case 0: e = match_url(r, p); break;
+        case 1: e = match_email(r, p); break;
+        case 2: e = match_ipv4(r, p); break;
+        case 3: e = match_mac(r, p); break;
+        case 4: e = match_hash(r, p); break;
+        case 5: e = match_cve(r, p); break;
+        default: e = match_hostname(r, p); break;
+      }
+      if (e < 0) continue;
+      ++count;
+      atomicAdd(&delta[e], -1);
+      const unsigned long long kk = span_key(e - p, 1 + k, p - r.lo);
+      best = kk > best ? kk : best;
     }
-    if (e < 0) continue;
-    ++count;
-    atomicAdd(&delta[e], -1);
-    const unsigned long long kk = span_key(e - p, 1 + k, p - r.lo);
-    best = kk > best ? kk : best;
-  }
-  if (count) {
-    atomicAdd(&delta[p], count);
-    atomicAdd(&starts[p], count);
-    atomicMax(&key[p], best);
+    if (count) {
+      atomicAdd(&delta[p], count);
+      atomicAdd(&starts[p], count);
+      atomicMax(&key[p], best);
+    }
   }
 }
 
@@ -388,7 +408,7 @@ void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64
   launch_fill_u8((uint8_t*)w.run_key, 0, (n + 1) * (int64_t)sizeof(unsigned long long), s);
   hipLaunchKernelGGL(rx_check_kernel, dim3(ceil_div(B + 1, 256)), dim3(256), 0, s, cu_bytes, B, n, err);
   if (n > 0)
-    hipLaunchKernelGGL(rx_match_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, text, cu_bytes, B, n, rt, w.delta,
+    hipLaunchKernelGGL(rx_match_kernel, dim3(ceil_div(n, kPerBlock)), dim3(256), 0, s, text, cu_bytes, B, n, rt, w.delta,
                        w.starts, w.key, err);
   if (ner && ner_cu && ner_cap > 0)
     hipLaunchKernelGGL(rx_ner_kernel, dim3(ceil_div(ner_cap, 256)), dim3(256), 0, s, ner, ner_cu, B, ner_cap,

@@ -15,6 +15,8 @@ It is a plain, slow, direct statement of what the path computes, in float64:
   (Sec. II, stage 3);
 * ``recognizers`` - pattern recognizers beside the NER model (Sec. II,
   stage 2) and the merge of overlapping detections;
+* ``fields`` - schema-aware whole-field spans without NER (configured
+  ``Field: value`` lines);
 * ``pipeline`` - the three composed over a packed batch of records.
 
 It shares no code with the GPU path; the only common module is ``synth``

@@ -241,6 +241,30 @@ anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, in
                             int32_t* d_cu_spans, void* d_workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Schema-aware whole-field spans, no NER (the paper's configuration that maps
+ * named fields straight to pseudonyms, bypassing inference: Sec. II; Sec. V,
+ * Table VI with and without it)
+ * ------------------------------------------------------------------------
+ * A line is a maximal run of bytes without '\n' inside one record.  It holds
+ * a field if its first ':' is directly followed by ' '; the name is the bytes
+ * before the ':', the value the bytes after ": " up to the end of the line.
+ * Each line whose name equals (byte for byte) a configured name and whose
+ * value is not empty gives one span of that name's type over the value.
+ *   d_text, d_cu_bytes, n_bytes  as in recognize_spans (ANON_ERR_TEXT if
+ *                                cu_bytes does not rise from 0 to n_bytes)
+ *   h_field_names  host, n_fields (0..64) names of 1..32 bytes, no ':' or '\n'
+ *   h_field_types  host int32 [n_fields], type index 1..n_types of each name
+ *   d_spans, span_cap, d_cu_spans  output as in decode_spans (record-major,
+ *                                  byte order; ANON_ERR_SPAN_CAP on overflow)
+ *   d_workspace  >= anon_field_workspace_size(n_bytes, B) bytes.
+ * The output feeds pseudonymize(). */
+anon_status anon_field_workspace_size(int64_t n_bytes, int32_t B, size_t* bytes);
+anon_status field_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, int32_t B, int64_t n_bytes,
+                        const char* const* h_field_names, const int32_t* h_field_types, int32_t n_fields,
+                        int32_t n_types, anon_span* d_spans, int32_t span_cap, int32_t* d_cu_spans,
+                        void* d_workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Pseudonyms (Sec. II stage 3)
  * ------------------------------------------------------------------------
  * A pseudonym cache holds the HMAC key, the slug length (0..64 lowercase hex

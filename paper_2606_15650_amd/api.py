@@ -76,6 +76,9 @@ _SIGS = {
     "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
     "decode_spans": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
     "anon_recognize_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
+    "anon_field_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
+    "field_spans": ([vp, vp, i32, i64, C.POINTER(C.c_char_p), C.POINTER(i32), i32, i32, vp, i32, vp, vp, sz, vp],
+                    i32),
     "recognize_spans": ([vp, vp, i32, i64, C.POINTER(i32), i32, vp, vp, i32, vp, i32, vp, vp, sz, vp], i32),
     "anon_pcache_create": ([vp, sz, i32, C.POINTER(C.c_char_p), i32, i64, i32, C.POINTER(vp)], i32),
     "anon_pcache_free": ([vp], None),
@@ -272,6 +275,23 @@ def recognize_spans(d_text, d_cu_bytes, B: int, n_bytes: int, rec_types, n_types
                                                     ptr(d_ner_spans), ptr(d_ner_cu), ner_cap, ptr(d_spans),
                                                     span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,
                                                     stream_handle(stream)))
+
+
+def field_workspace_size(n_bytes: int, B: int) -> int:
+    n = sz()
+    _check("anon_field_workspace_size", lib().anon_field_workspace_size(n_bytes, B, C.byref(n)))
+    return n.value
+
+
+def field_spans(d_text, d_cu_bytes, B: int, n_bytes: int, fields: dict, n_types: int, d_spans, span_cap: int,
+                d_cu_spans, d_workspace, ws_bytes: int, stream=None):
+    """fields: {field name (str or bytes): type index 1..n_types}."""
+    items = list(fields.items())
+    names = (C.c_char_p * max(1, len(items)))(*[k if isinstance(k, bytes) else k.encode() for k, _ in items])
+    types = (i32 * max(1, len(items)))(*[int(v) for _, v in items])
+    _check("field_spans", lib().field_spans(ptr(d_text), ptr(d_cu_bytes), B, n_bytes, names, types, len(items),
+                                            n_types, ptr(d_spans), span_cap, ptr(d_cu_spans), ptr(d_workspace),
+                                            ws_bytes, stream_handle(stream)))
 
 
 # ------------------------------------------------------------- pseudonyms --

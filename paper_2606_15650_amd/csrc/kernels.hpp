@@ -120,6 +120,26 @@ void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64
                       const anon_span* ner, const int* ner_cu, int ner_cap, int n_types, const RecogBuffers& w,
                       anon_span* out, int cap, int* cu_spans, uint32_t* err, hipStream_t s);
 
+// ---- schema-aware whole-field spans ----------------------------------------
+constexpr int kFieldNameMax = 32;
+constexpr int kFieldsMax = 64;
+struct FieldTable {  // passed by value to the kernels
+  uint8_t name[kFieldsMax][kFieldNameMax];
+  uint8_t len[kFieldsMax];
+  int type[kFieldsMax];
+  int n;
+};
+struct FieldBuffers {
+  uint8_t* rs;
+  int *flags, *excl;
+  void* temp;
+};
+FieldBuffers field_layout(int64_t n_bytes, Carver& k);
+size_t field_workspace_bytes(int64_t n_bytes);
+void launch_field_spans(const uint8_t* text, const int64_t* cu_bytes, int B, int64_t n_bytes, const FieldTable& ft,
+                        const FieldBuffers& w, anon_span* out, int cap, int* cu_spans, uint32_t* err,
+                        hipStream_t s);
+
 // Shape of a created model (the struct itself is private to the runtime).
 const anon_model_config* model_config(const anon_model* m);
 

@@ -841,6 +841,49 @@ anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, in
   return ANON_OK;
 }
 
+anon_status anon_field_workspace_size(int64_t n_bytes, int32_t B, size_t* bytes) {
+  if (!bytes || n_bytes < 0 || B < 0) return set_error(ANON_EINVAL, "bad arguments");
+  *bytes = field_workspace_bytes(n_bytes);
+  return ANON_OK;
+}
+
+anon_status field_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, int32_t B, int64_t n_bytes,
+                        const char* const* h_field_names, const int32_t* h_field_types, int32_t n_fields,
+                        int32_t n_types, anon_span* d_spans, int32_t span_cap, int32_t* d_cu_spans,
+                        void* d_workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (B < 0 || n_bytes < 0 || span_cap < 0) return set_error(ANON_EINVAL, "negative size");
+  if (B == 0 && n_bytes != 0) return set_error(ANON_EINVAL, "n_bytes > 0 with no records");
+  if (n_bytes >= (int64_t(1) << 31) - 2) return set_error(ANON_EINVAL, "n_bytes must be below 2^31 - 2");
+  if (n_types < 1 || n_types > 127) return set_error(ANON_EINVAL, "n_types must be in [1, 127]");
+  if (n_fields < 0 || n_fields > kFieldsMax) return set_error(ANON_EINVAL, "n_fields must be in [0, 64]");
+  if (n_fields > 0 && (!h_field_names || !h_field_types)) return set_error(ANON_EINVAL, "field table is NULL");
+  FieldTable ft{};
+  ft.n = n_fields;
+  for (int k = 0; k < n_fields; ++k) {
+    const char* nm = h_field_names[k];
+    if (!nm) return set_error(ANON_EINVAL, "field name is NULL");
+    const size_t L = strlen(nm);
+    if (L < 1 || L > (size_t)kFieldNameMax) return set_error(ANON_EINVAL, "field names must have 1..32 bytes");
+    for (size_t i = 0; i < L; ++i)
+      if (nm[i] == ':' || nm[i] == '\n') return set_error(ANON_EINVAL, "field names cannot hold ':' or newline");
+    if (h_field_types[k] < 1 || h_field_types[k] > n_types) return set_error(ANON_EINVAL, "field type outside [1, n_types]");
+    memcpy(ft.name[k], nm, L);
+    ft.len[k] = (uint8_t)L;
+    ft.type[k] = h_field_types[k];
+  }
+  if (!d_cu_spans || !d_cu_bytes) return set_error(ANON_EINVAL, "cu arrays are NULL");
+  if (n_bytes > 0 && !d_text) return set_error(ANON_EINVAL, "text is NULL");
+  if (span_cap > 0 && !d_spans) return set_error(ANON_EINVAL, "spans is NULL");
+  Carver k(d_workspace, ws_bytes);
+  const FieldBuffers w = field_layout(n_bytes, k);
+  if (!d_workspace || !k.ok()) return set_error(ANON_ECAPACITY, "workspace too small");
+  launch_field_spans(d_text, d_cu_bytes, B, n_bytes, ft, w, d_spans, span_cap, d_cu_spans, error_word_ptr(),
+                     (hipStream_t)stream);
+  ANON_HIP_CHECK(hipGetLastError());
+  return ANON_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------- pseudonyms ----

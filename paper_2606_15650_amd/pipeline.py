@@ -107,6 +107,24 @@ class Pipeline:
                             spans, cap, cu_spans, ws, ws.numel(), stream)
         return spans, cu_spans, cap
 
+    def fields(self, db: DeviceBatch, config: dict, span_cap: int | None = None, stream=None):
+        """Whole-field spans of the configured ``Field: value`` lines, without NER
+        (config: field name -> type index).  A field needs at least 4 bytes
+        ("x: v" and a line break), so n_bytes / 4 + 1 spans always fit."""
+        cap = (db.n_bytes // 4 + 1) if span_cap is None else span_cap
+        spans = torch.empty((max(cap, 1), 3), dtype=torch.int64, device=self.device)
+        cu_spans = torch.empty(db.B + 1, dtype=torch.int32, device=self.device)
+        ws = self._buf("fd", api.field_workspace_size(db.n_bytes, db.B))
+        api.field_spans(db.text, db.cu_bytes, db.B, db.n_bytes, config, self.n_types, spans, cap, cu_spans, ws,
+                        ws.numel(), stream)
+        return spans, cu_spans, cap
+
+    def step_fields(self, db: DeviceBatch, config: dict, stream=None):
+        """The schema-configured path: whole-field spans, then substitution (no NER)."""
+        spans, cu_spans, cap = self.fields(db, config, stream=stream)
+        out, cu_out = self.pseudonymize(db, spans, cu_spans, cap, stream=stream)
+        return spans, cu_spans, out, cu_out
+
     def out_capacity(self, db: DeviceBatch, span_cap: int) -> int:
         longest = max(len(n) for n in self.cache.type_names)
         return db.n_bytes + span_cap * (2 + longest + 1 + self.cache.slug) + 1

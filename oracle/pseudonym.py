@@ -55,3 +55,52 @@ def pseudonymize_batch(text: bytes, cu_bytes, spans: np.ndarray, n_records: int,
         per[r].append((t, b, e))
     return [substitute(text[int(cu[r]):int(cu[r + 1])], per[r], type_names, key, slug_len)
             for r in range(n_records)]
+
+
+# Per-type preservation and the entity <-> pseudonym mapping.
+#
+# The paper decouples detection from the replacement policy: chosen entity
+# types can be preserved (Sec. II), and the mapping of entities to
+# pseudonyms is persisted with the entity type, the original, the slug, the
+# full hash and when the entity was first and last seen (Sec. II, stage 4).
+# Readings: a preserved type's spans are left as they are; the mapping holds
+# one row per distinct entity of at most 96 bytes (the device table's entry
+# size) pseudonymized with the table enabled, with the smallest type index it
+# was pseudonymized under (an entity's bytes, not its type, determine the
+# hash), and "seen" counted in pseudonymize calls numbered from 1; rows are
+# ordered by first call, then by bytes.
+
+def preserve_spans(spans, preserve) -> list:
+    """The spans (type, begin, end) whose type is not preserved."""
+    keep = set(preserve)
+    return [s for s in spans if s[0] not in keep]
+
+
+MAX_TABLE_ENTITY = 96
+
+
+def mapping_rows(calls, type_names, key: bytes, slug_len: int, preserve=()) -> list[dict]:
+    """Mapping after a sequence of calls; each call is (text, cu_bytes, spans rows
+    (record, type, begin, end)), every span valid."""
+    rows: dict[bytes, dict] = {}
+    keep_out = set(preserve)
+    for c, (text, cu_bytes, spans) in enumerate(calls, start=1):
+        for r, t, b, e in np.asarray(spans, dtype=np.int64).reshape(-1, 4).tolist():
+            if t in keep_out:
+                continue
+            ent = text[int(cu_bytes[r]) + b:int(cu_bytes[r]) + e]
+            if len(ent) > MAX_TABLE_ENTITY:
+                continue
+            row = rows.get(ent)
+            if row is None:
+                full = hmac_hex(key, ent)
+                rows[ent] = {"entity_type": type_names[t - 1], "type": t, "original": ent,
+                             "slug": full[:slug_len], "full_hash": full, "first_seen": c, "last_seen": c}
+            else:
+                if t < row["type"]:
+                    row["type"], row["entity_type"] = t, type_names[t - 1]
+                row["last_seen"] = c
+    out = sorted(rows.values(), key=lambda d: (d["first_seen"], d["original"]))
+    for d in out:
+        del d["type"]
+    return out

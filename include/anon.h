@@ -287,6 +287,32 @@ anon_status anon_pcache_set_enabled(anon_pcache* cache, int32_t enabled);
  * last clear.  Synchronises the device. */
 anon_status anon_pcache_stats(anon_pcache* cache, int64_t* lookups, int64_t* hits, int64_t* entries);
 
+/* Types to preserve (the paper's per-type control, Sec. II): spans of these
+ * types are left as they are by later pseudonymize() calls (their bytes are
+ * copied, no pseudonym, no table entry).  The list replaces the previous one;
+ * n = 0 preserves nothing.  Types outside 1..n_types are rejected. */
+anon_status anon_pcache_set_preserve(anon_pcache* cache, const int32_t* h_types, int32_t n);
+
+/* The entity <-> pseudonym mapping held by the table (the paper's persisted
+ * mapping: type, original, slug, full hash, first and last seen; Sec. II
+ * stage 4).  One row per distinct entity of at most 96 bytes met by
+ * pseudonymize() with the table enabled since creation or the last clear
+ * (all of them while the table has room): the smallest type index it was
+ * pseudonymized under, its bytes, the full HMAC-SHA256 digest (the slug is
+ * its first slug_hex lowercase hex digits) and the first and last call that
+ * met it (calls are numbered from 1 per cache; a clear restarts the count).
+ * Rows are ordered by first call, then by bytes.  Writes min(cap, total)
+ * rows to h_out (host) and the total to *n_entries; synchronises the device. */
+typedef struct {
+  int32_t type;
+  int32_t len;
+  uint8_t bytes[96];
+  uint8_t digest[32];
+  uint32_t first_call;
+  uint32_t last_call;
+} anon_mapping;
+anon_status anon_pcache_export(anon_pcache* cache, anon_mapping* h_out, int64_t cap, int64_t* n_entries);
+
 /* Substitute every span of every record.
  *   d_text      uint8 record bytes back to back; record b is
  *               d_text[cu_bytes[b] .. cu_bytes[b+1])

@@ -85,6 +85,8 @@ _SIGS = {
     "anon_pcache_clear": ([vp, vp], i32),
     "anon_pcache_set_enabled": ([vp, i32], i32),
     "anon_pcache_stats": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], i32),
+    "anon_pcache_set_preserve": ([vp, C.POINTER(i32), i32], i32),
+    "anon_pcache_export": ([vp, vp, i64, C.POINTER(i64)], i32),
     "anon_pseudonymize_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
     "pseudonymize": ([vp, vp, vp, i32, vp, vp, i32, vp, i64, vp, vp, sz, vp], i32),
     "anon_server_start": ([vp, vp, C.POINTER(ServerConfigC), C.POINTER(vp)], i32),
@@ -295,6 +297,11 @@ def field_spans(d_text, d_cu_bytes, B: int, n_bytes: int, fields: dict, n_types:
 
 
 # ------------------------------------------------------------- pseudonyms --
+class _Mapping(C.Structure):
+    _fields_ = [("type", i32), ("len", i32), ("bytes", C.c_uint8 * 96), ("digest", C.c_uint8 * 32),
+                ("first_call", C.c_uint32), ("last_call", C.c_uint32)]
+
+
 class PseudonymCache:
     """HMAC key, slug length, type names and the device entity->digest table."""
 
@@ -318,6 +325,26 @@ class PseudonymCache:
         a, b, c = i64(), i64(), i64()
         _check("anon_pcache_stats", lib().anon_pcache_stats(self.handle, C.byref(a), C.byref(b), C.byref(c)))
         return {"lookups": a.value, "hits": b.value, "entries": c.value}
+
+    def set_preserve(self, types):
+        """Types (names or 1-based indices) whose spans are left as they are."""
+        idx = [self.type_names.index(t) + 1 if isinstance(t, str) else int(t) for t in types]
+        arr = (i32 * max(1, len(idx)))(*idx)
+        _check("anon_pcache_set_preserve", lib().anon_pcache_set_preserve(self.handle, arr, len(idx)))
+
+    def export(self) -> list[dict]:
+        """The entity <-> pseudonym mapping held by the table (see anon_pcache_export)."""
+        n = i64()
+        _check("anon_pcache_export", lib().anon_pcache_export(self.handle, None, 0, C.byref(n)))
+        rows = (_Mapping * max(1, n.value))()
+        _check("anon_pcache_export", lib().anon_pcache_export(self.handle, C.addressof(rows), n.value, C.byref(n)))
+        out = []
+        for r in rows[:n.value]:
+            full = bytes(r.digest).hex()
+            out.append({"entity_type": self.type_names[r.type - 1], "original": bytes(r.bytes[:r.len]),
+                        "slug": full[:self.slug], "full_hash": full, "first_seen": r.first_call,
+                        "last_seen": r.last_call})
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -134,7 +134,9 @@ __device__ inline void hmac_sha256(const PcacheDev& pc, const uint8_t* msg, int6
   sha256_compress(out, w);
 }
 
-// Table entry: state, length, fingerprint, entity bytes, digest.
+// Table entry: state, length, fingerprint, entity bytes, digest, and for the
+// mapping export the smallest type the entity was pseudonymized under and the
+// first and last call that met it.
 constexpr int kMaxEntity = 96;
 struct __align__(16) Entry {
   uint32_t state;  // 0 empty, 1 being written, 2 ready
@@ -142,8 +144,20 @@ struct __align__(16) Entry {
   uint64_t fp;
   uint8_t bytes[kMaxEntity];
   uint32_t digest[8];
+  int32_t type;
+  uint32_t first, last, pad;
 };
-static_assert(sizeof(Entry) == 144, "entry layout");
+static_assert(sizeof(Entry) == 160 && sizeof(Entry) == sizeof(PcacheEntryView), "entry layout");
+
+__device__ __forceinline__ bool preserved(const PcacheDev& pc, int type) {
+  return (pc.preserve[(type >> 5) & 3] >> (type & 31)) & 1u;
+}
+
+// A later meeting of a ready entry: keep the smallest type and the last call.
+__device__ __forceinline__ void touch(Entry* e, int type, uint32_t call) {
+  atomicMin(&e->type, type);
+  atomicMax(&e->last, call);
+}
 constexpr int kMaxProbe = 32;
 
 __device__ inline uint64_t fingerprint(const uint8_t* p, int len) {
@@ -179,7 +193,12 @@ __global__ void ps_layout_kernel(PcacheDev pc, const int64_t* __restrict__ cu_by
     const anon_span sp = spans[s];
     const bool ok = sp.record == b && sp.type >= 1 && sp.type <= pc.n_types && sp.begin >= prev_end &&
                     sp.end >= sp.begin && sp.end <= in_len;
-    if (ok) {
+    if (ok && preserved(pc, sp.type)) {
+      // a preserved type: the span's bytes are copied like the text around it
+      sp_out[s] = prev_end + acc;
+      sp_plen[s] = 0;
+      sp_in_end[s] = prev_end;
+    } else if (ok) {
       const int plen = 2 + (pc.name_off[sp.type] - pc.name_off[sp.type - 1]) + tail;
       sp_out[s] = sp.begin + acc;
       sp_plen[s] = plen;
@@ -223,6 +242,7 @@ __global__ void ps_hash_kernel(PcacheDev pc, const uint8_t* __restrict__ text, c
         for (int k = 0; k < 8; ++k) dg[k] = e->digest[k];
         have = true;
         atomicAdd(&pc.counters[1], 1ull);
+        touch(e, sp.type, pc.call);
         break;
       }
     }
@@ -241,11 +261,16 @@ __global__ void ps_hash_kernel(PcacheDev pc, const uint8_t* __restrict__ text, c
           for (int k = 0; k < len; ++k) e->bytes[k] = msg[k];
 #pragma unroll
           for (int k = 0; k < 8; ++k) e->digest[k] = dg[k];
+          e->type = sp.type;
+          e->first = e->last = pc.call;
           __hip_atomic_store(&e->state, 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           atomicAdd(&pc.counters[2], 1ull);
           break;
         }
-        if (expected == 2 && e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) break;
+        if (expected == 2 && e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) {
+          touch(e, sp.type, pc.call);
+          break;
+        }
       }
     }
   }

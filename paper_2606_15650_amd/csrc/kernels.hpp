@@ -87,6 +87,17 @@ struct PcacheDev {
   const int* name_off;    // [n_types + 1]
   unsigned long long* counters;  // [0] lookups, [1] hits, [2] inserts
   int enabled;
+  uint32_t preserve[4];   // bit t: spans of type t are left as they are
+  uint32_t call;          // number of this pseudonymize call on the cache (1-based)
+};
+// Host view of the table entries (anon_pcache_export).
+struct PcacheEntryView {
+  uint32_t state, len;
+  uint64_t fp;
+  uint8_t bytes[96];
+  uint32_t digest[8];
+  int32_t type;
+  uint32_t first, last, pad;
 };
 size_t pcache_entry_bytes();
 bool hmac_selftest();

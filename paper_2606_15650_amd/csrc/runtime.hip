@@ -5,7 +5,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "kernels.hpp"
@@ -892,6 +895,7 @@ struct anon_pcache {
   PcacheDev dev;
   int64_t capacity;
   void* mem = nullptr;
+  std::atomic<uint32_t> calls{0};  // pseudonymize calls since creation or the last clear
 };
 
 extern "C" {
@@ -978,6 +982,62 @@ anon_status anon_pcache_clear(anon_pcache* p, void* stream) {
   launch_fill_u8(p->dev.table, 0, p->capacity * (int64_t)pcache_entry_bytes(), s);
   launch_fill_u8((uint8_t*)p->dev.counters, 0, 4 * sizeof(unsigned long long), s);
   ANON_HIP_CHECK(hipGetLastError());
+  p->calls = 0;
+  return ANON_OK;
+}
+
+anon_status anon_pcache_set_preserve(anon_pcache* p, const int32_t* h_types, int32_t n) {
+  clear_error();
+  if (!p) return set_error(ANON_EINVAL, "cache is NULL");
+  if (n < 0 || (n > 0 && !h_types)) return set_error(ANON_EINVAL, "bad type list");
+  uint32_t m[4] = {0, 0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    const int t = h_types[i];
+    if (t < 1 || t > p->dev.n_types) return set_error(ANON_EINVAL, "type outside [1, n_types]");
+    m[t >> 5] |= 1u << (t & 31);
+  }
+  memcpy(p->dev.preserve, m, sizeof(m));
+  return ANON_OK;
+}
+
+anon_status anon_pcache_export(anon_pcache* p, anon_mapping* h_out, int64_t cap, int64_t* n_entries) {
+  clear_error();
+  if (!p || !n_entries) return set_error(ANON_EINVAL, "NULL argument");
+  if (cap < 0 || (cap > 0 && !h_out)) return set_error(ANON_EINVAL, "bad output buffer");
+  ANON_HIP_CHECK(hipSetDevice(p->device));
+  ANON_HIP_CHECK(hipDeviceSynchronize());
+  std::vector<PcacheEntryView> tab((size_t)p->capacity);
+  if (p->capacity > 0)
+    ANON_HIP_CHECK(hipMemcpy(tab.data(), p->dev.table, tab.size() * sizeof(PcacheEntryView), hipMemcpyDeviceToHost));
+  // an insert race can leave two entries for one entity: merge them
+  std::map<std::string, anon_mapping> merged;
+  for (const PcacheEntryView& e : tab) {
+    if (e.state != 2 || e.len > 96) continue;
+    const std::string k((const char*)e.bytes, e.len);
+    auto it = merged.find(k);
+    if (it == merged.end()) {
+      anon_mapping m{};
+      m.type = e.type;
+      m.len = (int32_t)e.len;
+      memcpy(m.bytes, e.bytes, e.len);
+      for (int w = 0; w < 8; ++w)
+        for (int b = 0; b < 4; ++b) m.digest[4 * w + b] = (uint8_t)(e.digest[w] >> (24 - 8 * b));
+      m.first_call = e.first;
+      m.last_call = e.last;
+      merged.emplace(k, m);
+    } else {
+      it->second.type = std::min(it->second.type, e.type);
+      it->second.first_call = std::min(it->second.first_call, e.first);
+      it->second.last_call = std::max(it->second.last_call, e.last);
+    }
+  }
+  std::vector<anon_mapping> out;
+  out.reserve(merged.size());
+  for (auto& kv : merged) out.push_back(kv.second);
+  std::stable_sort(out.begin(), out.end(),
+                   [](const anon_mapping& a, const anon_mapping& b) { return a.first_call < b.first_call; });
+  *n_entries = (int64_t)out.size();
+  for (int64_t i = 0; i < std::min(cap, (int64_t)out.size()); ++i) h_out[i] = out[(size_t)i];
   return ANON_OK;
 }
 
@@ -1044,11 +1104,12 @@ anon_status pseudonymize(anon_pcache* p, const uint8_t* d_text, const int64_t* d
   ANON_HIP_CHECK(hipSetDevice(p->device));
   hipStream_t s = (hipStream_t)stream;
   uint32_t* err = error_word_ptr();
-  launch_ps_layout(p->dev, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, out_len, sp_out, sp_plen, sp_in_end, err,
-                   s);
+  PcacheDev dev = p->dev;
+  dev.call = ++p->calls;
+  launch_ps_layout(dev, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, out_len, sp_out, sp_plen, sp_in_end, err, s);
   launch_exclusive_scan_i64(out_len, d_cu_out, B, temp, s);
-  launch_ps_hash(p->dev, d_text, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, sp_plen, dig, s);
-  launch_ps_write(p->dev, d_text, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, sp_out, sp_plen, sp_in_end, dig,
+  launch_ps_hash(dev, d_text, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, sp_plen, dig, s);
+  launch_ps_write(dev, d_text, d_cu_bytes, B, d_spans, d_cu_spans, span_cap, sp_out, sp_plen, sp_in_end, dig,
                   d_cu_out, d_out, out_cap, err, s);
   ANON_HIP_CHECK(hipGetLastError());
   return ANON_OK;

@@ -1006,29 +1006,35 @@ anon_status anon_pcache_export(anon_pcache* p, anon_mapping* h_out, int64_t cap,
   if (cap < 0 || (cap > 0 && !h_out)) return set_error(ANON_EINVAL, "bad output buffer");
   ANON_HIP_CHECK(hipSetDevice(p->device));
   ANON_HIP_CHECK(hipDeviceSynchronize());
-  std::vector<PcacheEntryView> tab((size_t)p->capacity);
-  if (p->capacity > 0)
-    ANON_HIP_CHECK(hipMemcpy(tab.data(), p->dev.table, tab.size() * sizeof(PcacheEntryView), hipMemcpyDeviceToHost));
-  // an insert race can leave two entries for one entity: merge them
+  // the table is read in chunks of 64 Ki entries (10 MiB), whatever its size;
+  // an insert race can leave two entries for one entity: they are merged
+  const int64_t chunk = 1 << 16;
+  std::vector<PcacheEntryView> tab((size_t)std::min(chunk, std::max(p->capacity, (int64_t)1)));
   std::map<std::string, anon_mapping> merged;
-  for (const PcacheEntryView& e : tab) {
-    if (e.state != 2 || e.len > 96) continue;
-    const std::string k((const char*)e.bytes, e.len);
-    auto it = merged.find(k);
-    if (it == merged.end()) {
-      anon_mapping m{};
-      m.type = e.type;
-      m.len = (int32_t)e.len;
-      memcpy(m.bytes, e.bytes, e.len);
-      for (int w = 0; w < 8; ++w)
-        for (int b = 0; b < 4; ++b) m.digest[4 * w + b] = (uint8_t)(e.digest[w] >> (24 - 8 * b));
-      m.first_call = e.first;
-      m.last_call = e.last;
-      merged.emplace(k, m);
-    } else {
-      it->second.type = std::min(it->second.type, e.type);
-      it->second.first_call = std::min(it->second.first_call, e.first);
-      it->second.last_call = std::max(it->second.last_call, e.last);
+  for (int64_t c0 = 0; c0 < p->capacity; c0 += chunk) {
+    const int64_t cn = std::min(chunk, p->capacity - c0);
+    ANON_HIP_CHECK(hipMemcpy(tab.data(), p->dev.table + c0 * (int64_t)sizeof(PcacheEntryView),
+                             (size_t)cn * sizeof(PcacheEntryView), hipMemcpyDeviceToHost));
+    for (int64_t ei = 0; ei < cn; ++ei) {
+      const PcacheEntryView& e = tab[(size_t)ei];
+      if (e.state != 2 || e.len > 96) continue;
+      const std::string k((const char*)e.bytes, e.len);
+      auto it = merged.find(k);
+      if (it == merged.end()) {
+        anon_mapping m{};
+        m.type = e.type;
+        m.len = (int32_t)e.len;
+        memcpy(m.bytes, e.bytes, e.len);
+        for (int w = 0; w < 8; ++w)
+          for (int b = 0; b < 4; ++b) m.digest[4 * w + b] = (uint8_t)(e.digest[w] >> (24 - 8 * b));
+        m.first_call = e.first;
+        m.last_call = e.last;
+        merged.emplace(k, m);
+      } else {
+        it->second.type = std::min(it->second.type, e.type);
+        it->second.first_call = std::min(it->second.first_call, e.first);
+        it->second.last_call = std::max(it->second.last_call, e.last);
+      }
     }
   }
   std::vector<anon_mapping> out;

@@ -62,7 +62,7 @@ def test_mapping_export_after_three_calls(torch_dev):
     A = synth.generate_records(150, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 61)
     B = synth.generate_records(150, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 62)
     key = synth.make_key(0)
-    cache = make_cache(names, slug=12, capacity=1 << 16)
+    cache = make_cache(names, slug=12, capacity=1 << 17)  # two export chunks
     cache.set_preserve(["PORT"])
     port = names.index("PORT") + 1
     # long spans: whole lines of some records (beyond the table's 96 bytes)

@@ -57,7 +57,7 @@ enum {
   ANON_ERR_SPAN = 8,          /* span outside its record / overlapping (skipped)     */
   ANON_ERR_SPAN_CAP = 16,     /* more spans than span_cap (extra spans dropped)      */
   ANON_ERR_OUT_CAP = 32,      /* output larger than out_cap (output truncated)       */
-  ANON_ERR_TEXT = 64          /* cu_bytes malformed or a record of >= 16 MiB (recognize_spans) */
+  ANON_ERR_TEXT = 64          /* cu_bytes malformed (recognize_spans, field_spans) or a record of >= 16 MiB (recognize_spans) */
 };
 
 /* Encoder shape.  head_dim = hidden / n_heads must be 64; n_labels = 2*types+1. */

@@ -363,7 +363,9 @@ def main() -> int:
         with open(os.path.join(ROOT, "tests", "golden", f"fp8_scales_{wl.name}.json")) as f:
             scales = np.asarray(json.load(f)["scales"], np.float32).reshape(-1)
 
-    def run_path(precision: str, steps: int, warmup: int, prof: bool):
+    def run_path(precision: str, steps: int, warmup: int, prof: bool, extras: bool = False):
+        """Time `steps` whole-path steps; with extras, also the recognizer and
+        schema-field paths on the same resident batch."""
         model = api.Model(cfg, blob, precision, act_scales=scales if precision == "fp8" else None)
         cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
         pl = Pipeline(model, cache)
@@ -395,8 +397,8 @@ def main() -> int:
                 kern[k] = api.prof_read(k)
                 api.prof_enable(k, False)
         st = cache.stats()
-        rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if recog else None
-        fd = field_timing(pl, db, stream, 10) if recog else None
+        rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if extras else None
+        fd = field_timing(pl, db, stream, 10) if extras else None
         model.close()
         cache.close()
         return wall, per, kern, st, tiles, rx, fd
@@ -452,9 +454,8 @@ def main() -> int:
                 "ner_spans": int(cu_spans[-1].item()), "merged_spans": int(cu_r[-1].item()),
                 "recognizers": api.RECOGNIZERS}
 
-    recog = not a.no_recognizers
-    wall, per, kern, cstats, tiles, rx, fd = run_path(wl.precision, a.steps, a.warmup, prof=True)
-    recog = False
+    wall, per, kern, cstats, tiles, rx, fd = run_path(wl.precision, a.steps, a.warmup, prof=True,
+                                                      extras=not a.no_recognizers)
     tokens_per_s = T * a.steps / wall
     # dominant kernel class (largest total time) against its roofline
     gemm_tok = gemm_flops_per_token(cfg)

@@ -176,8 +176,7 @@ __device__ int64_t match_cve(const Rec& r, int64_t p) {
 }
 
 constexpr int kRecognizers = 7;
-constexpr int kPerBlock = 256;                 // start bytes per match workgroup (one per thread)
-constexpr int kWin = 1 + kPerBlock + 1024;      // staged bytes (1 before, 1024 ahead)
+constexpr int kWin = 1 + 256 + 1024;  // staged bytes per match workgroup (1 before, 1024 ahead)
 struct RecTypes {
   int t[kRecognizers];  // type index per recognizer, 0 = off
 };
@@ -226,57 +225,89 @@ __global__ __launch_bounds__(256) void rx_clear_kernel(int* delta, int* starts, 
   }
 }
 
+// Every enabled rule at p; candidates go into the delta/start/key arrays.
+__device__ void match_all(const Rec& r, int64_t p, const RecTypes& rt, int* delta, int* starts,
+                          unsigned long long* key) {
+  int count = 0;
+  unsigned long long best = 0;
+#pragma unroll
+  for (int k = 0; k < kRecognizers; ++k) {
+    if (rt.t[k] == 0) continue;
+    int64_t e;
+    switch (k) {
+      case 0: e = match_url(r, p); break;
+      case 1: e = match_email(r, p); break;
+      case 2: e = match_ipv4(r, p); break;
+      case 3: e = match_mac(r, p); break;
+      case 4: e = match_hash(r, p); break;
+      case 5: e = match_cve(r, p); break;
+      default: e = match_hostname(r, p); break;
+    }
+    if (e < 0) continue;
+    ++count;
+    atomicAdd(&delta[e], -1);
+    const unsigned long long kk = span_key(e - p, 1 + k, p - r.lo);
+    best = kk > best ? kk : best;
+  }
+  if (count) {
+    atomicAdd(&delta[p], count);
+    atomicAdd(&starts[p], count);
+    atomicMax(&key[p], best);
+  }
+}
+
+__device__ __forceinline__ bool is_alnum(uint8_t c) { return is_digit(c) || is_letter(c); }
+
+// A rule can start at p only on a LOCAL byte (URL 'h', IPv4/MAC/hash/CVE
+// word bytes, e-mail LOCAL, hostname LABEL) whose predecessor in the record
+// is not alphanumeric (the word-boundary rules exclude a word byte before
+// it, the e-mail rule a LOCAL byte, the hostname rule a LABEL byte or dot).
+// Each workgroup first collects its 256 bytes that pass this test, then runs
+// the rules on them with the lanes packed: most bytes sit inside words, and
+// trying them all left most lanes of a wave idle behind a few long scans.
+// A record's first byte whose predecessor (the previous record's last byte)
+// is alphanumeric fails the test here and is tried by rx_recstart_kernel.
 __global__ __launch_bounds__(256) void rx_match_kernel(const uint8_t* __restrict__ text,
                                                        const int64_t* __restrict__ cu, int B, int64_t n,
                                                        RecTypes rt, int* delta, int* starts,
-                                                       unsigned long long* key, uint32_t* err) {
-  // the workgroup's kPerBlock start bytes, the byte before them and 1024
-  // bytes of lookahead, staged in LDS (coalesced loads)
+                                                       unsigned long long* key) {
+  // the workgroup's 256 start bytes, the byte before them and 1024 bytes of
+  // lookahead, staged in LDS (coalesced loads)
   __shared__ uint8_t win[kWin];
-  const int64_t p0 = (int64_t)blockIdx.x * kPerBlock;
+  __shared__ int cand[256];
+  __shared__ int ncand;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
   const int64_t wlo = p0 > 0 ? p0 - 1 : 0;
   const int64_t whi = min(wlo + kWin, n);
   for (int64_t i = wlo + threadIdx.x; i < whi; i += 256) win[i - wlo] = text[i];
+  if (threadIdx.x == 0) ncand = 0;
   __syncthreads();
-  // positions p0 + tid + 256 j (one when kPerBlock = 256; more per thread
-  // measured slower): one record search, then a forward walk
-  int b = -1;
-  for (int j = 0; j < kPerBlock / 256; ++j) {
-    const int64_t p = p0 + threadIdx.x + 256 * j;
-    if (p >= n) return;
-    if (b < 0) b = find_record(cu, B, p);
-    while (b + 1 < B && cu[b + 1] <= p) ++b;
+  const int64_t p = p0 + threadIdx.x;
+  if (p < n && is_local(win[p - wlo]) && !(p > 0 && is_alnum(win[p - 1 - wlo])))
+    cand[atomicAdd(&ncand, 1)] = threadIdx.x;
+  __syncthreads();
+  const int nc = ncand;
+  for (int i = threadIdx.x; i < nc; i += 256) {
+    const int64_t q = p0 + cand[i];
+    const int b = find_record(cu, B, q);
     int64_t lo, hi;
     record_bounds(cu, b, n, lo, hi);
-    if (p < lo || p >= hi) continue;  // only with a malformed cu_bytes
-    const Rec r{text, lo, hi, win, wlo, whi};
-    int count = 0;
-    unsigned long long best = 0;
-#pragma unroll
-    for (int k = 0; k < kRecognizers; ++k) {
-      if (rt.t[k] == 0) continue;
-      int64_t e;
-      switch (k) {
-        case 0: e = match_url(r, p); break;
-        case 1: e = match_email(r, p); break;
-        case 2: e = match_ipv4(r, p); break;
-        case 3: e = match_mac(r, p); break;
-        case 4: e = match_hash(r, p); break;
-        case 5: e = match_cve(r, p); break;
-        default: e = match_hostname(r, p); break;
-      }
-      if (e < 0) continue;
-      ++count;
-      atomicAdd(&delta[e], -1);
-      const unsigned long long kk = span_key(e - p, 1 + k, p - r.lo);
-      best = kk > best ? kk : best;
-    }
-    if (count) {
-      atomicAdd(&delta[p], count);
-      atomicAdd(&starts[p], count);
-      atomicMax(&key[p], best);
-    }
+    if (q < lo || q >= hi) continue;  // only with a malformed cu_bytes
+    match_all(Rec{text, lo, hi, win, wlo, whi}, q, rt, delta, starts, key);
   }
+}
+
+// Record starts whose previous byte is alphanumeric (see rx_match_kernel).
+__global__ __launch_bounds__(256) void rx_recstart_kernel(const uint8_t* __restrict__ text,
+                                                          const int64_t* __restrict__ cu, int B, int64_t n,
+                                                          RecTypes rt, int* delta, int* starts,
+                                                          unsigned long long* key) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  int64_t lo, hi;
+  record_bounds(cu, b, n, lo, hi);
+  if (hi <= lo || lo == 0 || !is_alnum(text[lo - 1]) || !is_local(text[lo])) return;
+  match_all(Rec{text, lo, hi, nullptr, 0, 0}, lo, rt, delta, starts, key);
 }
 
 // NER spans (record-relative [begin, end)) join the candidates.
@@ -407,9 +438,12 @@ void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64
   // written in full by rx_flags_kernel
   launch_fill_u8((uint8_t*)w.run_key, 0, (n + 1) * (int64_t)sizeof(unsigned long long), s);
   hipLaunchKernelGGL(rx_check_kernel, dim3(ceil_div(B + 1, 256)), dim3(256), 0, s, cu_bytes, B, n, err);
-  if (n > 0)
-    hipLaunchKernelGGL(rx_match_kernel, dim3(ceil_div(n, kPerBlock)), dim3(256), 0, s, text, cu_bytes, B, n, rt, w.delta,
-                       w.starts, w.key, err);
+  if (n > 0) {
+    hipLaunchKernelGGL(rx_match_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, text, cu_bytes, B, n, rt, w.delta,
+                       w.starts, w.key);
+    hipLaunchKernelGGL(rx_recstart_kernel, dim3(ceil_div(B, 256)), dim3(256), 0, s, text, cu_bytes, B, n, rt,
+                       w.delta, w.starts, w.key);
+  }
   if (ner && ner_cu && ner_cap > 0)
     hipLaunchKernelGGL(rx_ner_kernel, dim3(ceil_div(ner_cap, 256)), dim3(256), 0, s, ner, ner_cu, B, ner_cap,
                        cu_bytes, n, n_types, w.delta, w.starts, w.key, w.ner_type, err);

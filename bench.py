@@ -437,9 +437,35 @@ def main() -> int:
         st = cache.stats()
         rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if extras else None
         fd = field_timing(pl, db, stream, 10) if extras else None
+        gr = graph_timing(pl, db, stream, max(2, steps // 2)) if extras else None
         model.close()
         cache.close()
-        return wall, per, kern, st, tiles, rx, fd
+        return wall, per, kern, st, tiles, rx, fd, gr
+
+    def graph_timing(pl, db, stream, steps: int) -> dict:
+        """ner_forward over the batch as one HIP graph (ner_forward_capture)
+        against the same call launched kernel by kernel; labels compared."""
+        lab_e, _, mg_e = pl.ner(db, stream=stream)
+        ws = pl._buf("ner_graph", pl.model.workspace_size(db.T, db.B))
+        lab_g = torch.empty_like(lab_e)
+        mg_g = torch.empty_like(mg_e)
+        g = api.ner_forward_capture(pl.model, db.ids, db.cu, db.B, db.T, lab_g, None, mg_g, ws, ws.numel())
+        g.launch(stream)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(lab_e, lab_g) and torch.equal(mg_e, mg_g))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            pl.ner(db, stream=stream)
+        ev[1].record(stream)
+        ev[2].record(stream)
+        for _ in range(steps):
+            g.launch(stream)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        g.close()
+        return {"eager_ner_ms": ev[0].elapsed_time(ev[1]) / steps, "graph_ner_ms": ev[2].elapsed_time(ev[3]) / steps,
+                "labels_and_margins_equal": same}
 
     def field_timing(pl, db, stream, steps: int) -> dict:
         """The schema-configured path (whole-field spans of the generator's
@@ -492,7 +518,7 @@ def main() -> int:
                 "ner_spans": int(cu_spans[-1].item()), "merged_spans": int(cu_r[-1].item()),
                 "recognizers": api.RECOGNIZERS}
 
-    wall, per, kern, cstats, tiles, rx, fd = run_path(wl.precision, a.steps, a.warmup, prof=True,
+    wall, per, kern, cstats, tiles, rx, fd, gr = run_path(wl.precision, a.steps, a.warmup, prof=True,
                                                       extras=not a.no_recognizers)
     tokens_per_s = T * a.steps / wall
     # dominant kernel class (largest total time) against its roofline
@@ -552,8 +578,10 @@ def main() -> int:
         out["with_recognizers"] = rx
     if fd is not None:
         out["schema_fields"] = fd
+    if gr is not None:
+        out["ner_graph"] = gr
     if not a.no_fp32 and wl.precision != "fp32":
-        w32, per32, _, _, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
+        w32, per32, _, _, _, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
         tps32 = T * max(2, a.steps // 4) / w32
         out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
     if not a.no_cpu:

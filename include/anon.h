@@ -130,6 +130,26 @@ anon_status ner_forward(anon_model* model, const int32_t* d_ids, const int32_t* 
                         int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
                         size_t ws_bytes, void* stream);
 
+/* The NER forward pass (Sec. II stage 2) recorded as one HIP graph.
+ * ner_forward_capture records ner_forward with exactly these arguments (same
+ * meaning, layout and checks as ner_forward) on a private stream and
+ * instantiates the result; nothing is computed by the call itself.
+ * anon_graph_launch then runs the whole layer stack and the classifier on
+ * `stream` as one launch.  The graph holds the device pointers, B, T and the
+ * model's tile configuration as they were at capture: between launches the
+ * caller may rewrite the contents of d_ids and d_cu_seqlens (a new batch of
+ * exactly B records and T tokens), and every launch gives the same results
+ * as ner_forward on the buffers' contents at that time.  The model, the
+ * workspace and the buffers must outlive the graph; launches that overlap
+ * share the workspace and race.  Kernel timing (anon_prof_enable) must be
+ * off during the capture (ANON_EINVAL otherwise); T == 0 is ANON_EINVAL. */
+typedef struct anon_graph anon_graph;
+anon_status ner_forward_capture(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                                int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                                size_t ws_bytes, anon_graph** out);
+anon_status anon_graph_launch(anon_graph* graph, void* stream);
+void anon_graph_free(anon_graph* graph);
+
 /* GEMM tile autotuner.  Times every tile configuration that fits each of the
  * four encoder GEMMs (0 QKV, 1 output projection, 2 FFN1, 3 FFN2) on T rows,
  * using d_workspace (>= anon_ner_workspace_size(T, 1) bytes; overwritten) as

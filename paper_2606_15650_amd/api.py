@@ -71,6 +71,9 @@ _SIGS = {
     "anon_ner_workspace_size": ([vp, i32, i32, C.POINTER(sz)], i32),
     "ner_forward": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_encoder_hidden": ([vp, vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
+    "ner_forward_capture": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
+    "anon_graph_launch": ([vp, vp], i32),
+    "anon_graph_free": ([vp], None),
     "anon_ner_windowed_workspace_size": ([vp, vp, i32, i32, i32, C.POINTER(sz)], i32),
     "ner_forward_windowed": ([vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
@@ -222,6 +225,39 @@ def ner_forward(model: Model, d_ids, d_cu_seqlens, B: int, T: int, d_labels, d_l
     _check("ner_forward", lib().ner_forward(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T, ptr(d_labels),
                                             ptr(d_logits), ptr(d_margin), ptr(d_workspace), ws_bytes,
                                             stream_handle(stream)))
+
+
+class ForwardGraph:
+    """ner_forward recorded as one HIP graph (``ner_forward_capture``): each
+    ``launch`` runs the layer stack on the capture's buffers as they are at
+    that time.  Keeps the model and the buffers alive while it exists."""
+
+    def __init__(self, handle: int, keep: tuple):
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check("anon_graph_launch", lib().anon_graph_launch(self.handle, stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().anon_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ner_forward_capture(model: Model, d_ids, d_cu_seqlens, B: int, T: int, d_labels, d_logits=None,
+                        d_margin=None, d_workspace=None, ws_bytes: int = 0) -> ForwardGraph:
+    h = vp()
+    _check("ner_forward_capture",
+           lib().ner_forward_capture(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T, ptr(d_labels),
+                                     ptr(d_logits), ptr(d_margin), ptr(d_workspace), ws_bytes, C.byref(h)))
+    return ForwardGraph(h.value, (model, d_ids, d_cu_seqlens, d_labels, d_logits, d_margin, d_workspace))
 
 
 def encoder_hidden(model: Model, d_ids, d_cu_seqlens, B: int, T: int, n_layers: int, d_hidden, d_workspace,

@@ -510,6 +510,75 @@ anon_status ner_forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu
   return ANON_OK;
 }
 
+// The layer stack as one HIP graph: ner_forward recorded on a private
+// stream and instantiated once, so that a batch shape seen again costs one
+// launch instead of one per kernel.  The forward makes no host round trip
+// and allocates nothing once the device error word exists, and every
+// clear is a kernel, so the recording holds kernel nodes only.
+struct anon_graph {
+  int device;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+anon_status ner_forward_capture(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                                int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                                size_t ws_bytes, anon_graph** out) {
+  clear_error();
+  if (!out) return set_error(ANON_EINVAL, "out is NULL");
+  *out = nullptr;
+  anon_status st = check_batch(m, d_ids, d_cu_seqlens, B, T);
+  if (st != ANON_OK) return st;
+  if (T == 0) return set_error(ANON_EINVAL, "nothing to capture: the batch has no tokens");
+  if (!d_labels) return set_error(ANON_EINVAL, "labels is NULL");
+  if (!d_workspace || ws_bytes < enc_ws_bytes(m, T, B)) return set_error(ANON_ECAPACITY, "workspace too small");
+  for (int kc = 0; kc < KC_COUNT; ++kc)
+    if (g_prof.enabled[kc]) return set_error(ANON_EINVAL, "kernel timing is enabled; disable it to capture");
+  ANON_HIP_CHECK(hipSetDevice(m->device));
+  if (!error_word_ptr()) return set_error(ANON_EDEVICE, "cannot allocate the device error word");
+  hipStream_t cs;
+  ANON_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return set_error(ANON_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  st = ner_forward(m, d_ids, d_cu_seqlens, B, T, d_labels, d_logits, d_margin, d_workspace, ws_bytes, cs);
+  const std::string fwd_err = anon_last_error();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (st != ANON_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (st != ANON_OK) return set_error(st, "capture: " + fwd_err);
+    return set_error(ANON_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return set_error(ANON_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *out = new anon_graph{m->device, g, x};
+  return ANON_OK;
+}
+
+anon_status anon_graph_launch(anon_graph* g, void* stream) {
+  clear_error();
+  if (!g) return set_error(ANON_EINVAL, "graph is NULL");
+  ANON_HIP_CHECK(hipSetDevice(g->device));
+  ANON_HIP_CHECK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return ANON_OK;
+}
+
+void anon_graph_free(anon_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
 static ElemType prec_type(anon_precision p) {
   return p == ANON_FP32 ? ET_F32 : (p == ANON_BF16 ? ET_BF16 : ET_FP8);
 }

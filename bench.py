@@ -10,8 +10,9 @@ before the timed region starts.
 Prints one JSON line.  Besides the headline tokens/s it reports the plain FP32
 path on the same batch (the speedup baseline), per-step p50/p99 latency, the
 dominant kernel against the MFMA roofline (timed with HIP events on its launch
-stream during the timed steps), and the FP64 oracle's throughput on a bounded
-sample of the same workload on the host cores.
+stream during the timed steps), the serving loop's p50/p99 request latency at
+100 req/s (6 s of Poisson arrivals), and the FP64 oracle's throughput on a
+bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -97,7 +98,7 @@ def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
                       f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
 
 
-def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0) -> dict:
+def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None) -> dict:
     """Continuous-batching server under Poisson arrivals (serving workload).
 
     Requests hold U{1..200} records with the base workload's length
@@ -180,7 +181,7 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0) -> dict:
                         "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                         "tokens_per_s": tok / (t_last - t_first), "offered_tokens_per_s": offered,
                         "failed": sum(1 for d in done if d[4] != 0), "wall_s": wall})
-        print(json.dumps({"serve_partial": results[-1]}), flush=True)
+        print(json.dumps({"serve_partial": results[-1]}), file=log or sys.stdout, flush=True)
     model.close()
     cache.close()
     return {"metric": "serving p50/p99 request latency", "unit": "ms", "workload": "serve_bf16",
@@ -353,6 +354,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving run (100 req/s) of the default line")
     ap.add_argument("--no-recognizers", action="store_true",
                     help="skip the timings of the recognizer and schema-field paths")
     a = ap.parse_args()
@@ -584,6 +587,15 @@ def main() -> int:
         w32, per32, _, _, _, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
         tps32 = T * max(2, a.steps // 4) / w32
         out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
+    if not a.no_serve and wl.name == "base_bf16":
+        # request latency under streaming load (the serving workload at one
+        # rate, short); `--serve RATES` runs the full sweep
+        sv = serve_bench([100.0], 6.0, 1.5, log=sys.stderr)
+        r = sv["rates"][0]
+        out["serving"] = {"workload": sv["workload"], "rate_req_s": r["rate_req_s"], "requests": r["requests"],
+                          "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tokens_per_s": r["tokens_per_s"],
+                          "offered_tokens_per_s": r["offered_tokens_per_s"], "failed": r["failed"],
+                          "seconds": 6.0, "config": sv["config"]}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, rb, W, key, a.cpu_budget)
     print(json.dumps(out), flush=True)

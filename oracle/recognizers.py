@@ -25,12 +25,18 @@ Readings taken here (the GPU path takes the same):
   CVE       ``CVE-`` + 4 digits + ``-`` + 4..7 digits, at word boundaries;
   HOSTNAME  a dotted LABEL sequence not preceded by a LABEL byte or a dot,
             ending at a label equal to one of a fixed list of top-level
-            labels and not followed by a LABEL byte (the longest such).
+            labels and not followed by a LABEL byte (the longest such);
+  IPV6      an IPv6 address in one of the text forms of RFC 4291 section 2.2:
+            the maximal run of hex digits, ``:`` and ``.`` that starts at a
+            hex digit or ``:`` not preceded by a word byte, ``:`` or ``.``,
+            without its trailing dots, must be such an address and must not
+            be followed by a word byte.  It emits the IP address type.
 
-  Each rule is the match, at one start position, of a regular expression
-  (``PATTERNS`` below; the tests compare rule and expression at every
-  position of random texts).  Every position where a rule matches gives one
-  candidate span.
+  Each of the first seven rules is the match, at one start position, of a
+  regular expression (``PATTERNS`` below; the tests compare rule and
+  expression at every position of random texts); the IPv6 rule is pinned to
+  Python's ``ipaddress`` parser instead.  Every position where a rule
+  matches gives one candidate span.
 * Overlap resolution: NER spans and recognizer candidates that share at
   least one byte are merged into their union (chains merge transitively;
   spans that only touch stay apart).  The merged span takes the type of its
@@ -39,7 +45,9 @@ Readings taken here (the GPU path takes the same):
 """
 from __future__ import annotations
 
-RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME"]
+RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6"]
+# entity type each recognizer emits by default
+RECOGNIZER_TYPE = {r: r for r in RECOGNIZERS} | {"IPV6": "IP_ADDRESS"}
 TOP_LABELS = [b"corp", b"lan", b"intra", b"net", b"org", b"local", b"example", b"internal"]
 
 _W = frozenset(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789_")
@@ -187,16 +195,64 @@ def match_hostname(t: bytes, p: int) -> int:
     return -1
 
 
+def _dotted_quad(g: bytes) -> bool:
+    parts = g.split(b".")
+    return len(parts) == 4 and all(
+        1 <= len(x) <= 3 and all(c in _DIGIT for c in x) and (len(x) == 1 or x[0] != ord("0")) and int(x) <= 255
+        for x in parts)
+
+
+def ipv6_text_valid(s: bytes) -> bool:
+    """Whether s is an IPv6 address in a text form of RFC 4291 section 2.2:
+    eight groups of 1-4 hex digits separated by ':', where one '::' may stand
+    for one or more zero groups and the last 32 bits may be written as a
+    dotted quad (octets without leading zeros)."""
+    halves = s.split(b"::")
+    if len(halves) > 2:
+        return False
+    groups = []
+    for h in halves:
+        groups.append(h.split(b":") if h else [])
+    flat = [g for gs in groups for g in gs]
+    n = 0
+    for i, g in enumerate(flat):
+        if b"." in g:
+            # only the last group, and only where the text ends with it
+            if i != len(flat) - 1 or not s.endswith(g) or not _dotted_quad(g):
+                return False
+            n += 2
+        elif 1 <= len(g) <= 4 and all(c in _HEX for c in g):
+            n += 1
+        else:
+            return False
+    return n <= 7 if len(halves) == 2 else n == 8
+
+
+def match_ipv6(t: bytes, p: int) -> int:
+    if t[p] not in _HEX and t[p] != ord(":"):
+        return -1
+    if p > 0 and (t[p - 1] in _W or t[p - 1] in b":."):
+        return -1
+    e = p
+    while e < len(t) and (t[e] in _HEX or t[e] in b":."):
+        e += 1
+    while e > p and t[e - 1] == ord("."):
+        e -= 1
+    if not ipv6_text_valid(t[p:e]) or not _word_end(t, e):
+        return -1
+    return e
+
+
 MATCHERS = {
     "URL": match_url, "EMAIL_ADDRESS": match_email, "IP_ADDRESS": match_ipv4, "MAC_ADDRESS": match_mac,
-    "HASH": match_hash, "CVE_ID": match_cve, "HOSTNAME": match_hostname,
+    "HASH": match_hash, "CVE_ID": match_cve, "HOSTNAME": match_hostname, "IPV6": match_ipv6,
 }
 
 
 def recognizer_types(type_names) -> list[int]:
     """Type index (1-based, as in the label scheme) of each recognizer, 0 if the model has no such type."""
     names = list(type_names)
-    return [names.index(r) + 1 if r in names else 0 for r in RECOGNIZERS]
+    return [names.index(RECOGNIZER_TYPE[r]) + 1 if RECOGNIZER_TYPE[r] in names else 0 for r in RECOGNIZERS]
 
 
 def candidates(t: bytes, rec_types) -> list[tuple[int, int, int, int]]:

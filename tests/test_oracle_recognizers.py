@@ -1,6 +1,7 @@
 """Pins of the recognizer oracle: each rule against Python's regular-expression
 engine at every position of seeded random texts, hand-made overlap-resolution
 cases, and coverage of the generator's gold entities."""
+import ipaddress
 import random
 import re
 
@@ -23,10 +24,12 @@ PIECES = {
     "CVE_ID": [b"CVE-", b"2021", b"-", b"12345", b"1", b"a", b" ", b"CVE-2021-1234567", b"_", b"cve-"],
     "HOSTNAME": [b"a", b"b1", b"-", b".", b"corp", b"lan", b"local", b"net", b"org1", b" ", b"@", b"x.internal",
                  b"/", b"Corp"],
+    "IPV6": [b"fe80", b"::", b":", b":", b"1", b"0db8", b"FFFF", b"0", b"12345", b"1.2.3.4", b"01.2.3.4", b".",
+             b" ", b"g", b"_", b"2001:db8::1", b"0:0:0:0:0:0:0:1", b"a:b:c:d:e:f:1:2", b"::ffff:10.0.0.1", b"\n"],
 }
 
 
-@pytest.mark.parametrize("name", R.RECOGNIZERS)
+@pytest.mark.parametrize("name", [n for n in R.RECOGNIZERS if n in R.PATTERNS])
 def test_rule_equals_regular_expression_at_every_position(name):
     pat = re.compile(R.PATTERNS[name])
     rule = R.MATCHERS[name]
@@ -42,6 +45,63 @@ def test_rule_equals_regular_expression_at_every_position(name):
     assert hits > 100, hits  # the texts do exercise matches
 
 
+def _ipaddress_accepts(s: bytes) -> bool:
+    try:
+        ipaddress.IPv6Address(s.decode("ascii"))
+        return True
+    except ValueError:
+        return False
+
+
+def test_ipv6_validator_equals_ipaddress():
+    """The oracle's own reading of the RFC 4291 text forms accepts exactly
+    what Python's ipaddress parser accepts: every string of up to 6 bytes
+    over a small alphabet, and random assemblies of groups, colons and
+    dotted quads."""
+    alphabet = [b"0", b"f", b"1", b":", b"."]
+    n_valid = 0
+    strings = [b""]
+    for _ in range(6):
+        strings = [x + a for x in strings for a in alphabet]
+        for x in strings:
+            v = R.ipv6_text_valid(x)
+            assert v == _ipaddress_accepts(x), x
+            n_valid += v
+    pieces = [b"0", b"1", b"ab", b"ffff", b"0db8", b"12345", b":", b":", b"::", b"1.2.3.4", b"255.0.0.1",
+              b"256.1.1.1", b"01.2.3.4", b".", b"1.2.3"]
+    rng = random.Random(17)
+    for _ in range(40000):
+        x = b"".join(rng.choice(pieces) for _ in range(rng.randint(1, 18)))
+        v = R.ipv6_text_valid(x)
+        assert v == _ipaddress_accepts(x), x
+        n_valid += v
+    assert n_valid > 1000, n_valid
+
+
+_RUN = re.compile(rb"(?<![A-Za-z0-9_:.])[0-9A-Fa-f:][0-9A-Fa-f:.]*")
+
+
+def test_ipv6_rule_equals_run_and_ipaddress_at_every_position():
+    """The rule against a second formulation: a regular expression finds the
+    run, the trailing dots are stripped, ipaddress judges the rest, and no
+    word byte may follow."""
+    rng = random.Random(23)
+    hits = 0
+    for _ in range(3000):
+        t = b"".join(rng.choice(PIECES["IPV6"]) for _ in range(rng.randint(1, 14)))
+        for p in range(len(t)):
+            m = _RUN.match(t, p)
+            want = -1
+            if m:
+                sub = m.group().rstrip(b".")
+                e = p + len(sub)
+                if _ipaddress_accepts(sub) and (e == len(t) or t[e] not in b"_" and not chr(t[e]).isalnum()):
+                    want = e
+            assert R.match_ipv6(t, p) == want, (t, p)
+            hits += want >= 0
+    assert hits > 300, hits
+
+
 def test_rules_on_written_examples():
     cases = {
         "IP_ADDRESS": [(b"host 10.0.0.255 up", 5, 15), (b"v1.2.3.4", 1, -1), (b"1.2.3.256", 0, -1),
@@ -52,6 +112,10 @@ def test_rules_on_written_examples():
         "URL": [(b"see https://a.corp/kb now", 4, 21), (b"xhttps://a", 1, -1)],
         "EMAIL_ADDRESS": [(b"to j.doe@mail.example.", 3, 21), (b"a@b.c1", 0, -1), (b"a@b.corp.x1", 0, 8)],
         "HOSTNAME": [(b"at db-1.site.corp.", 3, 17), (b"a.b.org1", 0, -1), (b"a.corp.lan", 0, 10)],
+        "IPV6": [(b"gw fe80::1%eth0", 3, 10), (b"(2001:db8::8a2e:370:7334).", 1, 24), (b"::", 0, 2),
+                 (b"ip ::ffff:10.0.0.1.", 3, 18), (b"00:1a:2b:3c:4d:5e", 0, -1), (b"12:30:45", 0, -1),
+                 (b"1:2:3:4:5:6:7:8", 0, 15), (b"1:2:3:4:5:6:7:8:9", 0, -1), (b"x::1", 1, -1),
+                 (b"fe80::1g", 0, -1), (b"::ffff:01.2.3.4", 0, -1), (b"1::2::3", 0, -1)],
     }
     for name, rows in cases.items():
         for t, p, e in rows:

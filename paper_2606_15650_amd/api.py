@@ -290,14 +290,16 @@ def decode_spans(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int
                                               stream_handle(stream)))
 
 
-# Recognizer order of recognize_spans (the type each emits is chosen per call).
-RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME"]
+# Recognizer order of recognize_spans (the type each emits is chosen per call),
+# and the entity type each emits by default.
+RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6"]
+RECOGNIZER_TYPE = {r: r for r in RECOGNIZERS} | {"IPV6": "IP_ADDRESS"}
 
 
 def recognizer_types(type_names) -> list[int]:
     """Type index (1-based) each recognizer emits for a model's type names; 0 = off."""
     names = list(type_names)
-    return [names.index(r) + 1 if r in names else 0 for r in RECOGNIZERS]
+    return [names.index(RECOGNIZER_TYPE[r]) + 1 if RECOGNIZER_TYPE[r] in names else 0 for r in RECOGNIZERS]
 
 
 def recognize_workspace_size(n_bytes: int, B: int) -> int:
@@ -308,7 +310,9 @@ def recognize_workspace_size(n_bytes: int, B: int) -> int:
 
 def recognize_spans(d_text, d_cu_bytes, B: int, n_bytes: int, rec_types, n_types: int, d_ner_spans, d_ner_cu,
                     ner_cap: int, d_spans, span_cap: int, d_cu_spans, d_workspace, ws_bytes: int, stream=None):
-    rt = (i32 * 7)(*[int(x) for x in rec_types])
+    if len(rec_types) != len(RECOGNIZERS):
+        raise ValueError(f"rec_types needs {len(RECOGNIZERS)} entries, one per recognizer")
+    rt = (i32 * len(RECOGNIZERS))(*[int(x) for x in rec_types])
     _check("recognize_spans", lib().recognize_spans(ptr(d_text), ptr(d_cu_bytes), B, n_bytes, rt, n_types,
                                                     ptr(d_ner_spans), ptr(d_ner_cu), ner_cap, ptr(d_spans),
                                                     span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,

@@ -2,7 +2,7 @@
 // transformer with regular-expression recognizers, Sec. II stage 2) and the
 // merge of overlapping detections into whole-entity spans.
 //
-// Seven recognizers, each a rule at one start byte of a record (W = word bytes
+// Eight recognizers, each a rule at one start byte of a record (W = word bytes
 // [A-Za-z0-9_], LABEL = [A-Za-z0-9-], LOCAL = [A-Za-z0-9._%+-]):
 //   0 URL       "http://" or "https://" at a word start, then >= 1 non-space bytes
 //   1 EMAIL     maximal LOCAL run, '@', >= 1 "label." groups, then an all-letter
@@ -14,6 +14,10 @@
 //   5 CVE       "CVE-" + 4 digits + '-' + 4..7 digits at word boundaries
 //   6 HOSTNAME  dotted LABEL run not preceded by LABEL or '.', ending at a label
 //               equal to one of eight top labels, not followed by LABEL (longest)
+//   7 IPV6      an address in an RFC 4291 (section 2.2) text form: the maximal
+//               run of hex digits, ':' and '.' from a hex digit or ':' not
+//               preceded by W, ':' or '.', without its trailing dots, not
+//               followed by W
 // Every start byte where a rule matches gives one candidate span.
 //
 // Merge: NER spans and candidates sharing a byte form one span, their union
@@ -175,7 +179,82 @@ __device__ int64_t match_cve(const Rec& r, int64_t p) {
   return (c >= 4 && c <= 7 && r.word_end(e)) ? e : -1;
 }
 
-constexpr int kRecognizers = 7;
+// Four octets separated by '.', exactly covering [i, end).
+__device__ bool dotted_quad(const Rec& r, int64_t i, int64_t end) {
+  for (int k = 0; k < 4; ++k) {
+    const int64_t e = octet(r, i);
+    if (e < 0) return false;
+    if (k == 3) return e == end;
+    if (e >= end || r.at(e) != '.') return false;
+    i = e + 1;
+  }
+  return false;
+}
+
+// The address text S = [p, s) is read group by group: 1-4 hex digits, a ':'
+// after every group but the last, one "::" at most (standing for at least
+// one zero group, so at most seven written groups), and a dotted quad, worth
+// two groups, only as the text's last group.  An address text is at most 45
+// bytes long, so a longer S is rejected while it is scanned.
+__device__ int64_t match_ipv6(const Rec& r, int64_t p) {
+  const uint8_t c0 = r.at(p);
+  if (!is_hex(c0) && c0 != ':') return -1;
+  if (p > r.lo) {
+    const uint8_t c = r.at(p - 1);
+    if (is_word(c) || c == ':' || c == '.') return -1;
+  }
+  // The first group has at most 4 hex digits and a ':' follows it (a lone
+  // group or a dotted quad alone is no address), so hashes, IPv4 addresses
+  // and words are rejected after at most 5 bytes.
+  int64_t e = p, s = p;
+  bool colon = false;
+  while (e < r.hi) {
+    const uint8_t c = r.at(e);
+    if (c == '.') {
+      if (!colon) return -1;
+      ++e;
+      continue;
+    }
+    if (c == ':') colon = true;
+    else if (!is_hex(c)) break;
+    else if (!colon && e - p >= 4) return -1;
+    s = ++e;
+    if (s - p > 45) return -1;
+  }
+  if (!colon || !r.word_end(s)) return -1;
+  int groups = 0;
+  bool dbl = false;
+  int64_t i = p;
+  if (c0 == ':') {
+    if (s - p < 2 || r.at(p + 1) != ':') return -1;
+    dbl = true;
+    i = p + 2;
+  }
+  while (i < s) {
+    int64_t j = i;
+    while (j < s && is_hex(r.at(j))) ++j;
+    if (j < s && r.at(j) == '.') {
+      if (!dotted_quad(r, i, s)) return -1;
+      groups += 2;
+      break;
+    }
+    if (j == i || j - i > 4) return -1;
+    ++groups;
+    i = j;
+    if (i == s) break;
+    ++i;  // the ':' after the group
+    if (i == s) return -1;
+    if (r.at(i) == ':') {
+      if (dbl) return -1;
+      dbl = true;
+      if (++i == s) break;
+    }
+  }
+  return (dbl ? groups <= 7 : groups == 8) ? s : -1;
+}
+
+constexpr int kRecognizers = kNumRecognizers;
+constexpr int kIpv6 = 7;  // index of the IPv6 rule, which runs in a kernel of its own
 constexpr int kWin = 1 + 256 + 1024;  // staged bytes per match workgroup (1 before, 1024 ahead)
 struct RecTypes {
   int t[kRecognizers];  // type index per recognizer, 0 = off
@@ -231,7 +310,7 @@ __device__ void match_all(const Rec& r, int64_t p, const RecTypes& rt, int* delt
   int count = 0;
   unsigned long long best = 0;
 #pragma unroll
-  for (int k = 0; k < kRecognizers; ++k) {
+  for (int k = 0; k < kIpv6; ++k) {
     if (rt.t[k] == 0) continue;
     int64_t e;
     switch (k) {
@@ -257,6 +336,7 @@ __device__ void match_all(const Rec& r, int64_t p, const RecTypes& rt, int* delt
 }
 
 __device__ __forceinline__ bool is_alnum(uint8_t c) { return is_digit(c) || is_letter(c); }
+
 
 // A rule can start at p only on a LOCAL byte (URL 'h', IPv4/MAC/hash/CVE
 // word bytes, e-mail LOCAL, hostname LABEL) whose predecessor in the record
@@ -308,6 +388,59 @@ __global__ __launch_bounds__(256) void rx_recstart_kernel(const uint8_t* __restr
   record_bounds(cu, b, n, lo, hi);
   if (hi <= lo || lo == 0 || !is_alnum(text[lo - 1]) || !is_local(text[lo])) return;
   match_all(Rec{text, lo, hi, nullptr, 0, 0}, lo, rt, delta, starts, key);
+}
+
+// The IPv6 rule over every byte, in a kernel of its own: its parser would
+// raise the register count of the other rules' kernel and halve its
+// occupancy.  An address starts with 1-4 hex digits or ':' and has a ':'
+// within its first 5 bytes, so a byte is tried only if a ':' follows it that
+// closely (read from the staged window, which holds the 4 bytes after every
+// start byte unless the text ends first); the rule itself then checks the
+// record bounds and its predecessor.  Its contributions add to the same
+// delta/start/key arrays with atomics, in any order.
+__global__ __launch_bounds__(256) void rx_ipv6_kernel(const uint8_t* __restrict__ text,
+                                                      const int64_t* __restrict__ cu, int B, int64_t n, int* delta,
+                                                      int* starts, unsigned long long* key) {
+  // an address is at most 45 bytes: 64 bytes of lookahead hold almost every
+  // candidate's run (reads past the window go to global memory)
+  constexpr int kWin6 = 1 + 256 + 64;
+  __shared__ uint8_t win[kWin6];
+  __shared__ int cand[256];
+  __shared__ int ncand;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t wlo = p0 > 0 ? p0 - 1 : 0;
+  const int64_t whi = min(wlo + kWin6, n);
+  for (int64_t i = wlo + threadIdx.x; i < whi; i += 256) win[i - wlo] = text[i];
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  const int64_t p = p0 + threadIdx.x;
+  if (p < n) {
+    bool pass = false;
+    for (int k = 0; k < 5 && p + k < whi; ++k) {
+      const uint8_t c = win[p + k - wlo];
+      if (c == ':') {
+        pass = true;
+        break;
+      }
+      if (!is_hex(c)) break;
+    }
+    if (pass) cand[atomicAdd(&ncand, 1)] = threadIdx.x;
+  }
+  __syncthreads();
+  const int nc = ncand;
+  for (int i = threadIdx.x; i < nc; i += 256) {
+    const int64_t q = p0 + cand[i];
+    const int b = find_record(cu, B, q);
+    int64_t lo, hi;
+    record_bounds(cu, b, n, lo, hi);
+    if (q < lo || q >= hi) continue;  // only with a malformed cu_bytes
+    const int64_t e = match_ipv6(Rec{text, lo, hi, win, wlo, whi}, q);
+    if (e < 0) continue;
+    atomicAdd(&delta[e], -1);
+    atomicAdd(&delta[q], 1);
+    atomicAdd(&starts[q], 1);
+    atomicMax(&key[q], span_key(e - q, 1 + kIpv6, q - lo));
+  }
 }
 
 // NER spans (record-relative [begin, end)) join the candidates.
@@ -427,7 +560,8 @@ RecogBuffers recog_layout(int64_t n, Carver& k) {
   return w;
 }
 
-void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64_t n, const int rec_types[7],
+void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64_t n,
+                      const int rec_types[kNumRecognizers],
                       const anon_span* ner, const int* ner_cu, int ner_cap, int n_types, const RecogBuffers& w,
                       anon_span* out, int cap, int* cu_spans, uint32_t* err, hipStream_t s) {
   RecTypes rt;
@@ -443,6 +577,9 @@ void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64
                        w.starts, w.key);
     hipLaunchKernelGGL(rx_recstart_kernel, dim3(ceil_div(B, 256)), dim3(256), 0, s, text, cu_bytes, B, n, rt,
                        w.delta, w.starts, w.key);
+    if (rt.t[kIpv6] != 0)
+      hipLaunchKernelGGL(rx_ipv6_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, text, cu_bytes, B, n, w.delta,
+                         w.starts, w.key);
   }
   if (ner && ner_cu && ner_cap > 0)
     hipLaunchKernelGGL(rx_ner_kernel, dim3(ceil_div(ner_cap, 256)), dim3(256), 0, s, ner, ner_cu, B, ner_cap,

@@ -161,7 +161,7 @@ extern "C" {
 
 const char* anon_last_error(void) { return t_last_error.c_str(); }
 
-int32_t anon_version(void) { return 1; }
+int32_t anon_version(void) { return 2; }
 
 anon_status anon_device_errors(int32_t device, uint32_t* flags, int32_t clear) {
   if (!flags) return set_error(ANON_EINVAL, "flags is NULL");
@@ -895,8 +895,8 @@ anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, in
   if (n_bytes >= (int64_t(1) << 31) - 2) return set_error(ANON_EINVAL, "n_bytes must be below 2^31 - 2");
   if (n_types < 1 || n_types > 127) return set_error(ANON_EINVAL, "n_types must be in [1, 127]");
   if (!h_rec_types) return set_error(ANON_EINVAL, "rec_types is NULL");
-  int rt[7];
-  for (int k = 0; k < 7; ++k) {
+  int rt[kNumRecognizers];
+  for (int k = 0; k < kNumRecognizers; ++k) {
     rt[k] = h_rec_types[k];
     if (rt[k] < 0 || rt[k] > n_types) return set_error(ANON_EINVAL, "recognizer type outside [0, n_types]");
   }

@@ -110,6 +110,30 @@ def test_recognizers_alone_on_adversarial_texts(torch_dev):
     assert got == want
 
 
+def test_ipv6_texts(torch_dev):
+    """Texts built from IPv6 pieces (addresses, '::' forms, dotted-quad tails,
+    near-misses, trailing dots, runs longer than any address) with the MAC,
+    hash and IPv4 rules on the same bytes."""
+    names = synth.TYPE_NAMES_17
+    rng = random.Random(29)
+    pool = PIECES["IPV6"] + [b"f" * 50, b"." * 40, b"0a:1b:2c:3d:4e:5f"]
+    seps = [b" ", b", ", b"\n", b"(", b") ", b"=", b". "]
+
+    def token():
+        return b"".join(rng.choice(pool) for _ in range(rng.randint(1, 3)))
+
+    recs = [b"".join(token() + rng.choice(seps) for _ in range(rng.randint(0, 12))) for _ in range(500)]
+    rb = _text_batch(recs, names)
+    cache = make_cache(names)
+    say(f"[recognize] {rb.n_records} IPv6 texts, {len(rb.text)} bytes")
+    cu_h, arr = _recognize_gpu(rb, cache)
+    got = _per_record(cu_h, arr, rb.n_records)
+    want = R.resolve_batch(rb.text, rb.cu_bytes, [[] for _ in range(rb.n_records)], names)
+    n_v6 = sum(1 for t in recs for p in range(len(t)) if R.match_ipv6(t, p) >= 0)
+    assert n_v6 > 300, n_v6
+    assert got == want
+
+
 def test_recognizers_merge_truncated_ner_spans(torch_dev):
     """Gold entities stand in for NER spans; a third of them are cut short
     (as an NER boundary error would), so the recognizers must extend them."""

@@ -30,12 +30,18 @@ Readings taken here (the GPU path takes the same):
             the maximal run of hex digits, ``:`` and ``.`` that starts at a
             hex digit or ``:`` not preceded by a word byte, ``:`` or ``.``,
             without its trailing dots, must be such an address and must not
-            be followed by a word byte.  It emits the IP address type.
+            be followed by a word byte.  It emits the IP address type;
+  CPE       a CPE name (the paper lists CPE strings among its entity kinds):
+            ``cpe:/`` (URI binding) or ``cpe:2.3:`` (formatted string) at a
+            word start, a part letter (``a``, ``h``, ``o``; in 2.3 also ``*``
+            or ``-``) not followed by a component byte, then the maximal run
+            of component bytes [A-Za-z0-9._~%*?!\\-] and ``:``.  It emits a
+            ``CPE`` type, so it is off for label sets without one.
 
-  Each of the first seven rules is the match, at one start position, of a
-  regular expression (``PATTERNS`` below; the tests compare rule and
-  expression at every position of random texts); the IPv6 rule is pinned to
-  Python's ``ipaddress`` parser instead.  Every position where a rule
+  Each rule but IPv6 is the match, at one start position, of a regular
+  expression (``PATTERNS`` below; the tests compare rule and expression at
+  every position of random texts); the IPv6 rule is pinned to Python's
+  ``ipaddress`` parser instead.  Every position where a rule
   matches gives one candidate span.
 * Overlap resolution: NER spans and recognizer candidates that share at
   least one byte are merged into their union (chains merge transitively;
@@ -45,7 +51,7 @@ Readings taken here (the GPU path takes the same):
 """
 from __future__ import annotations
 
-RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6"]
+RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6", "CPE"]
 # entity type each recognizer emits by default
 RECOGNIZER_TYPE = {r: r for r in RECOGNIZERS} | {"IPV6": "IP_ADDRESS"}
 TOP_LABELS = [b"corp", b"lan", b"intra", b"net", b"org", b"local", b"example", b"internal"]
@@ -68,6 +74,7 @@ PATTERNS = {
     "HASH": rb"\b(?:[0-9A-Fa-f]{64}|[0-9A-Fa-f]{40}|[0-9A-Fa-f]{32})\b",
     "CVE_ID": rb"\bCVE-[0-9]{4}-[0-9]{4,7}\b",
     "HOSTNAME": rb"(?<![A-Za-z0-9.-])(?:[A-Za-z0-9-]+\.)+(?:" + b"|".join(TOP_LABELS) + rb")(?![A-Za-z0-9-])",
+    "CPE": rb"\bcpe:(?:/[aho]|2\.3:[aho*-])(?![A-Za-z0-9._~%*?!\\-])[A-Za-z0-9._~%*?!\\:-]*",
 }
 
 
@@ -243,9 +250,31 @@ def match_ipv6(t: bytes, p: int) -> int:
     return e
 
 
+_CPE = frozenset(b"ABCDEFGHIJKLMNOPQRSTUVWXYZabcdefghijklmnopqrstuvwxyz0123456789._~%*?!\\-")
+
+
+def match_cpe(t: bytes, p: int) -> int:
+    if not _word_start(t, p):
+        return -1
+    if t.startswith(b"cpe:/", p):
+        q, parts = p + 5, b"aho"
+    elif t.startswith(b"cpe:2.3:", p):
+        q, parts = p + 8, b"aho*-"
+    else:
+        return -1
+    if q == len(t) or t[q] not in parts:
+        return -1
+    q += 1
+    if q < len(t) and t[q] in _CPE:
+        return -1
+    while q < len(t) and (t[q] in _CPE or t[q] == ord(":")):
+        q += 1
+    return q
+
+
 MATCHERS = {
     "URL": match_url, "EMAIL_ADDRESS": match_email, "IP_ADDRESS": match_ipv4, "MAC_ADDRESS": match_mac,
-    "HASH": match_hash, "CVE_ID": match_cve, "HOSTNAME": match_hostname, "IPV6": match_ipv6,
+    "HASH": match_hash, "CVE_ID": match_cve, "HOSTNAME": match_hostname, "IPV6": match_ipv6, "CPE": match_cpe,
 }
 
 

@@ -26,6 +26,8 @@ PIECES = {
                  b"/", b"Corp"],
     "IPV6": [b"fe80", b"::", b":", b":", b"1", b"0db8", b"FFFF", b"0", b"12345", b"1.2.3.4", b"01.2.3.4", b".",
              b" ", b"g", b"_", b"2001:db8::1", b"0:0:0:0:0:0:0:1", b"a:b:c:d:e:f:1:2", b"::ffff:10.0.0.1", b"\n"],
+    "CPE": [b"cpe:/", b"cpe:2.3:", b"cpe:/a:apache:http_server:2.4.41", b"a", b"h", b"o", b"x", b"*", b"-", b":",
+            b"::", b"apache", b"2.4.41", b"\\:", b" ", b"_", b"cpe", b"CPE:/", b".", b"\n", b"~", b"/", b"?"],
 }
 
 
@@ -116,6 +118,9 @@ def test_rules_on_written_examples():
                  (b"ip ::ffff:10.0.0.1.", 3, 18), (b"00:1a:2b:3c:4d:5e", 0, -1), (b"12:30:45", 0, -1),
                  (b"1:2:3:4:5:6:7:8", 0, 15), (b"1:2:3:4:5:6:7:8:9", 0, -1), (b"x::1", 1, -1),
                  (b"fe80::1g", 0, -1), (b"::ffff:01.2.3.4", 0, -1), (b"1::2::3", 0, -1)],
+        "CPE": [(b"(cpe:/a:apache:http_server:2.4.41) ", 1, 33), (b"cpe:2.3:o:microsoft:windows_10:1909:*:*:*:*", 0, 43),
+                (b"xcpe:/a:b", 1, -1), (b"cpe:/ab:c", 0, -1), (b"cpe:2.3:*", 0, 9), (b"cpe:/*:x", 0, -1),
+                (b"cpe:/a", 0, 6), (b"cpe:/a/b", 0, 6), (b"CPE:/a:b", 0, -1)],
     }
     for name, rows in cases.items():
         for t, p, e in rows:

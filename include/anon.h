@@ -223,7 +223,7 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
  * overlapping detections that are not merged: truncated entities and extra
  * pseudonyms)
  * ------------------------------------------------------------------------
- * Eight recognizers run over every byte of every record (W = [A-Za-z0-9_],
+ * Nine recognizers run over every byte of every record (W = [A-Za-z0-9_],
  * LABEL = [A-Za-z0-9-], LOCAL = [A-Za-z0-9._%+-]), in this order:
  *   0 URL        "http://" or "https://" at a word start, then >= 1 non-space bytes
  *   1 EMAIL      maximal LOCAL run, '@', >= 1 "label." groups, then an all-letter
@@ -241,6 +241,10 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
  *                digits, ':' and '.' from a hex digit or ':' not preceded by a
  *                word byte, ':' or '.', without its trailing dots, not followed
  *                by a word byte
+ *   8 CPE        "cpe:/" + a part in [aho] or "cpe:2.3:" + a part in [aho*-] at a
+ *                word start, the part not followed by a component byte
+ *                [A-Za-z0-9._~%*?!\-], then the maximal run of component bytes
+ *                and ':'
  * Every start byte where a rule matches gives a candidate span.  The NER spans
  * and the candidates that share a byte are merged into their union
  * (transitively; spans that only touch stay apart); the union takes the type
@@ -250,7 +254,7 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
  *                       (cu_bytes[0] = 0, cu_bytes[B] = n_bytes, records below
  *                       16 MiB; otherwise ANON_ERR_TEXT is raised)
  *   n_bytes      host copy of cu_bytes[B] (sizes the launch), below 2^31 - 2
- *   h_rec_types  int32 [8] host: type index (1..n_types) each recognizer emits,
+ *   h_rec_types  int32 [9] host: type index (1..n_types) each recognizer emits,
  *                0 switches it off
  *   d_ner_spans, d_ner_cu, ner_cap  decode_spans() output and its capacity
  *                (ner_cap = 0: recognizers alone; spans outside their record

@@ -292,7 +292,7 @@ def decode_spans(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int
 
 # Recognizer order of recognize_spans (the type each emits is chosen per call),
 # and the entity type each emits by default.
-RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6"]
+RECOGNIZERS = ["URL", "EMAIL_ADDRESS", "IP_ADDRESS", "MAC_ADDRESS", "HASH", "CVE_ID", "HOSTNAME", "IPV6", "CPE"]
 RECOGNIZER_TYPE = {r: r for r in RECOGNIZERS} | {"IPV6": "IP_ADDRESS"}
 
 

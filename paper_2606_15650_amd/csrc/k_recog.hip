@@ -2,7 +2,7 @@
 // transformer with regular-expression recognizers, Sec. II stage 2) and the
 // merge of overlapping detections into whole-entity spans.
 //
-// Eight recognizers, each a rule at one start byte of a record (W = word bytes
+// Nine recognizers, each a rule at one start byte of a record (W = word bytes
 // [A-Za-z0-9_], LABEL = [A-Za-z0-9-], LOCAL = [A-Za-z0-9._%+-]):
 //   0 URL       "http://" or "https://" at a word start, then >= 1 non-space bytes
 //   1 EMAIL     maximal LOCAL run, '@', >= 1 "label." groups, then an all-letter
@@ -18,6 +18,9 @@
 //               run of hex digits, ':' and '.' from a hex digit or ':' not
 //               preceded by W, ':' or '.', without its trailing dots, not
 //               followed by W
+//   8 CPE       "cpe:/" + part [aho] or "cpe:2.3:" + part [aho*-] at a word
+//               start, the part not followed by a component byte C =
+//               [A-Za-z0-9._~%*?!\-], then the maximal run of C and ':'
 // Every start byte where a rule matches gives one candidate span.
 //
 // Merge: NER spans and candidates sharing a byte form one span, their union
@@ -179,6 +182,27 @@ __device__ int64_t match_cve(const Rec& r, int64_t p) {
   return (c >= 4 && c <= 7 && r.word_end(e)) ? e : -1;
 }
 
+__device__ __forceinline__ bool is_cpe(uint8_t c) {
+  return is_digit(c) || is_letter(c) || c == '.' || c == '_' || c == '~' || c == '%' || c == '*' || c == '?' ||
+         c == '!' || c == '\\' || c == '-';
+}
+
+__device__ int64_t match_cpe(const Rec& r, int64_t p) {
+  if (!r.word_start(p)) return -1;
+  int64_t q;
+  bool v23;
+  if (r.has(p, "cpe:/", 5)) q = p + 5, v23 = false;
+  else if (r.has(p, "cpe:2.3:", 8)) q = p + 8, v23 = true;
+  else return -1;
+  if (q == r.hi) return -1;
+  const uint8_t part = r.at(q);
+  if (!(part == 'a' || part == 'h' || part == 'o' || (v23 && (part == '*' || part == '-')))) return -1;
+  ++q;
+  if (q < r.hi && is_cpe(r.at(q))) return -1;
+  while (q < r.hi && (is_cpe(r.at(q)) || r.at(q) == ':')) ++q;
+  return q;
+}
+
 // Four octets separated by '.', exactly covering [i, end).
 __device__ bool dotted_quad(const Rec& r, int64_t i, int64_t end) {
   for (int k = 0; k < 4; ++k) {
@@ -254,7 +278,9 @@ __device__ int64_t match_ipv6(const Rec& r, int64_t p) {
 }
 
 constexpr int kRecognizers = kNumRecognizers;
-constexpr int kIpv6 = 7;  // index of the IPv6 rule, which runs in a kernel of its own
+// the IPv6 and CPE rules run in a kernel of their own (rx_extra_kernel)
+constexpr int kIpv6 = 7;
+constexpr int kCpe = 8;
 constexpr int kWin = 1 + 256 + 1024;  // staged bytes per match workgroup (1 before, 1024 ahead)
 struct RecTypes {
   int t[kRecognizers];  // type index per recognizer, 0 = off
@@ -390,17 +416,19 @@ __global__ __launch_bounds__(256) void rx_recstart_kernel(const uint8_t* __restr
   match_all(Rec{text, lo, hi, nullptr, 0, 0}, lo, rt, delta, starts, key);
 }
 
-// The IPv6 rule over every byte, in a kernel of its own: its parser would
-// raise the register count of the other rules' kernel and halve its
-// occupancy.  An address starts with 1-4 hex digits or ':' and has a ':'
-// within its first 5 bytes, so a byte is tried only if a ':' follows it that
-// closely (read from the staged window, which holds the 4 bytes after every
-// start byte unless the text ends first); the rule itself then checks the
-// record bounds and its predecessor.  Its contributions add to the same
-// delta/start/key arrays with atomics, in any order.
-__global__ __launch_bounds__(256) void rx_ipv6_kernel(const uint8_t* __restrict__ text,
-                                                      const int64_t* __restrict__ cu, int B, int64_t n, int* delta,
-                                                      int* starts, unsigned long long* key) {
+// The IPv6 and CPE rules over every byte, in a kernel of their own: inlined
+// beside the other rules, either raises that kernel's register count from
+// 66 to over 110 VGPRs and nearly halves its occupancy.  Each has an exact
+// pre-filter on the staged window, which holds the 7 bytes after every start
+// byte unless the text ends first: an IPv6 address starts with 1-4 hex
+// digits or ':' and has a ':' within its first 5 bytes; a CPE name starts
+// with "cpe:".  The rules then check the record bounds and boundaries.
+// Contributions add to the same delta/start/key arrays with atomics, in any
+// order.
+__global__ __launch_bounds__(256) void rx_extra_kernel(const uint8_t* __restrict__ text,
+                                                       const int64_t* __restrict__ cu, int B, int64_t n, int use_ipv6,
+                                                       int use_cpe, int* delta, int* starts,
+                                                       unsigned long long* key) {
   // an address is at most 45 bytes: 64 bytes of lookahead hold almost every
   // candidate's run (reads past the window go to global memory)
   constexpr int kWin6 = 1 + 256 + 64;
@@ -416,14 +444,19 @@ __global__ __launch_bounds__(256) void rx_ipv6_kernel(const uint8_t* __restrict_
   const int64_t p = p0 + threadIdx.x;
   if (p < n) {
     bool pass = false;
-    for (int k = 0; k < 5 && p + k < whi; ++k) {
-      const uint8_t c = win[p + k - wlo];
-      if (c == ':') {
-        pass = true;
-        break;
+    if (use_ipv6) {
+      for (int k = 0; k < 5 && p + k < whi; ++k) {
+        const uint8_t c = win[p + k - wlo];
+        if (c == ':') {
+          pass = true;
+          break;
+        }
+        if (!is_hex(c)) break;
       }
-      if (!is_hex(c)) break;
     }
+    if (use_cpe && p + 3 < whi)
+      pass = pass || (win[p - wlo] == 'c' && win[p + 1 - wlo] == 'p' && win[p + 2 - wlo] == 'e' &&
+                      win[p + 3 - wlo] == ':');
     if (pass) cand[atomicAdd(&ncand, 1)] = threadIdx.x;
   }
   __syncthreads();
@@ -434,12 +467,27 @@ __global__ __launch_bounds__(256) void rx_ipv6_kernel(const uint8_t* __restrict_
     int64_t lo, hi;
     record_bounds(cu, b, n, lo, hi);
     if (q < lo || q >= hi) continue;  // only with a malformed cu_bytes
-    const int64_t e = match_ipv6(Rec{text, lo, hi, win, wlo, whi}, q);
-    if (e < 0) continue;
-    atomicAdd(&delta[e], -1);
-    atomicAdd(&delta[q], 1);
-    atomicAdd(&starts[q], 1);
-    atomicMax(&key[q], span_key(e - q, 1 + kIpv6, q - lo));
+    const Rec r{text, lo, hi, win, wlo, whi};
+    int count = 0;
+    unsigned long long best = 0;
+    const int64_t e6 = use_ipv6 ? match_ipv6(r, q) : -1;
+    if (e6 >= 0) {
+      ++count;
+      atomicAdd(&delta[e6], -1);
+      best = span_key(e6 - q, 1 + kIpv6, q - lo);
+    }
+    const int64_t ec = use_cpe ? match_cpe(r, q) : -1;
+    if (ec >= 0) {
+      ++count;
+      atomicAdd(&delta[ec], -1);
+      const unsigned long long kk = span_key(ec - q, 1 + kCpe, q - lo);
+      best = kk > best ? kk : best;
+    }
+    if (count) {
+      atomicAdd(&delta[q], count);
+      atomicAdd(&starts[q], count);
+      atomicMax(&key[q], best);
+    }
   }
 }
 
@@ -577,9 +625,9 @@ void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64
                        w.starts, w.key);
     hipLaunchKernelGGL(rx_recstart_kernel, dim3(ceil_div(B, 256)), dim3(256), 0, s, text, cu_bytes, B, n, rt,
                        w.delta, w.starts, w.key);
-    if (rt.t[kIpv6] != 0)
-      hipLaunchKernelGGL(rx_ipv6_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, text, cu_bytes, B, n, w.delta,
-                         w.starts, w.key);
+    if (rt.t[kIpv6] != 0 || rt.t[kCpe] != 0)
+      hipLaunchKernelGGL(rx_extra_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, text, cu_bytes, B, n,
+                         rt.t[kIpv6] != 0 ? 1 : 0, rt.t[kCpe] != 0 ? 1 : 0, w.delta, w.starts, w.key);
   }
   if (ner && ner_cu && ner_cap > 0)
     hipLaunchKernelGGL(rx_ner_kernel, dim3(ceil_div(ner_cap, 256)), dim3(256), 0, s, ner, ner_cu, B, ner_cap,

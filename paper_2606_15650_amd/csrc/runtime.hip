@@ -161,7 +161,7 @@ extern "C" {
 
 const char* anon_last_error(void) { return t_last_error.c_str(); }
 
-int32_t anon_version(void) { return 2; }
+int32_t anon_version(void) { return 3; }
 
 anon_status anon_device_errors(int32_t device, uint32_t* flags, int32_t clear) {
   if (!flags) return set_error(ANON_EINVAL, "flags is NULL");

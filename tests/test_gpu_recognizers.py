@@ -99,7 +99,7 @@ def _adversarial_records(n: int, seed: int) -> list[bytes]:
 
 
 def test_recognizers_alone_on_adversarial_texts(torch_dev):
-    names = synth.TYPE_NAMES_17
+    names = synth.TYPE_NAMES_17 + ["CPE"]  # all nine rules on
     rb = _text_batch(_adversarial_records(600, 5), names)
     cache = make_cache(names)
     say(f"[recognize] {rb.n_records} adversarial records, {len(rb.text)} bytes")
@@ -131,6 +131,27 @@ def test_ipv6_texts(torch_dev):
     want = R.resolve_batch(rb.text, rb.cu_bytes, [[] for _ in range(rb.n_records)], names)
     n_v6 = sum(1 for t in recs for p in range(len(t)) if R.match_ipv6(t, p) >= 0)
     assert n_v6 > 300, n_v6
+    assert got == want
+
+
+def test_cpe_texts(torch_dev):
+    """CPE names in both bindings, near-misses and neighbours, with a label
+    set that has a CPE type."""
+    names = synth.TYPE_NAMES_17 + ["CPE"]
+    rng = random.Random(31)
+    pool = PIECES["CPE"] + [b"cpe:/o:linux:linux_kernel:5.4", b"cpe:2.3:a:openbsd:openssh:8.2:*:*:*:*:*:*:*",
+                            b"10.0.0.1", b"https://x.corp/a"]
+    seps = [b" ", b", ", b"\n", b"(", b") ", b"="]
+    recs = [b"".join(b"".join(rng.choice(pool) for _ in range(rng.randint(1, 3))) + rng.choice(seps)
+                     for _ in range(rng.randint(0, 12))) for _ in range(500)]
+    rb = _text_batch(recs, names)
+    cache = make_cache(names)
+    say(f"[recognize] {rb.n_records} CPE texts, {len(rb.text)} bytes")
+    cu_h, arr = _recognize_gpu(rb, cache)
+    got = _per_record(cu_h, arr, rb.n_records)
+    want = R.resolve_batch(rb.text, rb.cu_bytes, [[] for _ in range(rb.n_records)], names)
+    n_cpe = sum(1 for t in recs for p in range(len(t)) if R.match_cpe(t, p) >= 0)
+    assert n_cpe > 300, n_cpe
     assert got == want
 
 

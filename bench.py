@@ -98,7 +98,8 @@ def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
                       f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
 
 
-def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None) -> dict:
+def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, streams: int = 3,
+                max_tok: int = 131072) -> dict:
     """Continuous-batching server under Poisson arrivals (serving workload).
 
     Requests hold U{1..200} records with the base workload's length
@@ -118,11 +119,10 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None) -
     W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
     model = api.Model(cfg, synth.weights_blob(cfg, W), "bf16")
     cache = api.PseudonymCache(synth.make_key(0), 10, pool.type_names, 1 << 20)
-    max_tok = 131072
     Pipeline(model, cache).autotune(max_tok, 1)
     results = []
     for rate in rates:
-        sv = api.Server(model, cache, hbm_budget_bytes=64 << 30, max_batch_tokens=max_tok, n_streams=3,
+        sv = api.Server(model, cache, hbm_budget_bytes=64 << 30, max_batch_tokens=max_tok, n_streams=streams,
                         max_queue=100000)
         rng = np.random.default_rng(seed + int(rate))
         # request = a run of consecutive pool records (wrapping), U{1..200} long
@@ -187,7 +187,7 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None) -
     return {"metric": "serving p50/p99 request latency", "unit": "ms", "workload": "serve_bf16",
             "config": {"model": "12L h768 BF16", "requests": "Poisson arrivals, U{1..200} records each, "
                        "lengths as base_bf16", "hbm_budget": "64 GiB", "max_batch_tokens": max_tok,
-                       "streams": 3}, "rates": results}
+                       "streams": streams}, "rates": results}
 
 
 def stream_bench(max_chunk_tokens: int = 2_000_000) -> dict:
@@ -353,6 +353,8 @@ def main() -> int:
     ap.add_argument("--serve", default="", help="comma-separated request rates: run the serving benchmark")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-streams", type=int, default=3, help="server slots (HIP streams)")
+    ap.add_argument("--serve-max-tokens", type=int, default=131072, help="tokens per micro-batch at most")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving run (100 req/s) of the default line")
@@ -365,7 +367,8 @@ def main() -> int:
         return 2
     if a.serve:
         rates = [float(x) for x in a.serve.split(",")]
-        print(json.dumps(serve_bench(rates, a.serve_seconds, a.serve_warmup)), flush=True)
+        print(json.dumps(serve_bench(rates, a.serve_seconds, a.serve_warmup, streams=a.serve_streams,
+                                     max_tok=a.serve_max_tokens)), flush=True)
         return 0
     if a.workload == "stream_bf16":
         print(json.dumps(stream_bench()), flush=True)

@@ -10,7 +10,7 @@ false negatives).
 
 Readings taken here (the GPU path takes the same):
 
-* Seven recognizers, each a rule over the bytes of one record, with W = the
+* Nine recognizers, each a rule over the bytes of one record, with W = the
   word bytes [A-Za-z0-9_], LABEL = [A-Za-z0-9-], LOCAL = [A-Za-z0-9._%+-]:
 
   URL       ``http://`` or ``https://`` at a word boundary, then the maximal

@@ -125,7 +125,7 @@ struct RecogBuffers {
 };
 RecogBuffers recog_layout(int64_t n_bytes, Carver& k);
 size_t recog_workspace_bytes(int64_t n_bytes);
-// rec_types: type index of each of the 7 recognizers (0 = off).  ner/ner_cu
+// rec_types: type index of each of the 9 recognizers (0 = off).  ner/ner_cu
 // may be null (no NER spans).
 constexpr int kNumRecognizers = 9;  // URL, e-mail, IPv4, MAC, hash, CVE, hostname, IPv6, CPE
 void launch_recognize(const uint8_t* text, const int64_t* cu_bytes, int B, int64_t n_bytes,

@@ -16,6 +16,7 @@ path can be held to: two evaluations that differ by at most d per logit can
 disagree on the argmax only where the top-2 margin is below 2d.
 
     python -m oracle.sensitivity base_bf16   -> tests/golden/sensitivity_base_bf16.json
+    python -m oracle.sensitivity base2_windowed_bf16   (the windowed BF16 test's case)
 """
 from __future__ import annotations
 
@@ -73,9 +74,38 @@ def measure(name: str) -> dict:
     }
 
 
+# Base widths with two layers, windowed as the dataset-scale stream is (512
+# tokens every 448), on records longer than one window: the case of the
+# windowed BF16 parity test, with its weights and records.
+WINDOWED = {"lengths": [1300, 513, 900, 200], "records_seed": 13, "weight_seed": 2, "window": 512, "stride": 448}
+
+
+def measure_windowed_base2() -> dict:
+    from oracle import pipeline as opipe
+    from synth.configs import ModelConfig
+    cfg = ModelConfig(n_layers=2, hidden=768, n_heads=12, ffn=3072, vocab=30522, n_labels=17)
+    W = synth.make_weights(cfg, WINDOWED["weight_seed"])
+    rb = synth.generate_records(len(WINDOWED["lengths"]), np.array(WINDOWED["lengths"]), cfg.n_types, cfg.vocab,
+                                WINDOWED["records_seed"])
+    win, st = WINDOWED["window"], WINDOWED["stride"]
+    zq, lq, mq = opipe.ner(W, cfg, rb.ids, rb.cu_seqlens, encoder.Precision("bf16"), win, st)
+    zp, lp, mp = opipe.ner(W, cfg, rb.ids, rb.cu_seqlens, None, win, st)
+    zn, ln, mn = opipe.ner(W, cfg, rb.ids, rb.cu_seqlens, _Perturbed("bf16", EPS, 1), win, st)
+    dn, dp = np.abs(zn - zq), np.abs(zq - zp)
+    return {
+        "source": "written by oracle/sensitivity.py (oracle only)",
+        "workload": "base2_windowed_bf16", "layers": cfg.n_layers, "hidden": cfg.hidden, "tokens": int(rb.n_tokens),
+        "case": WINDOWED, "perturbation": EPS,
+        "perturbed_vs_rounding_oracle": {"max": float(dn.max()), "rms": float(np.sqrt((dn ** 2).mean()))},
+        "rounding_oracle_vs_pure": {"max": float(dp.max()), "rms": float(np.sqrt((dp ** 2).mean()))},
+        "confident_label_flips_at_1e-2": int(((ln != lq) & (mq > 1e-2)).sum()),
+        "tokens_with_margin_above_1e-2": int((mq > 1e-2).sum()),
+    }
+
+
 if __name__ == "__main__":
     name = sys.argv[1] if len(sys.argv) > 1 else "base_bf16"
-    out = measure(name)
+    out = measure_windowed_base2() if name == "base2_windowed_bf16" else measure(name)
     path = os.path.join(ROOT, "tests", "golden", f"sensitivity_{name}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

@@ -165,3 +165,20 @@ def test_generator_gold_entities_are_covered():
             total += 1
             covered += any(sb <= b and e <= se for _, sb, se in spans)
     assert total > 50 and covered == total, (covered, total)
+
+
+def test_recognizer_type_mapping():
+    """IPv6 emits the IP address type; CPE is off unless the label set has a
+    CPE type; the binding's mapping equals the oracle's."""
+    from paper_2606_15650_amd import api
+    names = synth.TYPE_NAMES_17
+    rt = R.recognizer_types(names)
+    assert len(rt) == len(R.RECOGNIZERS) == 9
+    ip = names.index("IP_ADDRESS") + 1
+    assert rt[R.RECOGNIZERS.index("IP_ADDRESS")] == rt[R.RECOGNIZERS.index("IPV6")] == ip
+    assert rt[R.RECOGNIZERS.index("CPE")] == 0
+    with_cpe = names + ["CPE"]
+    assert R.recognizer_types(with_cpe)[R.RECOGNIZERS.index("CPE")] == len(with_cpe)
+    assert api.RECOGNIZERS == R.RECOGNIZERS
+    for ns in (names, synth.TYPE_NAMES_9, with_cpe):
+        assert api.recognizer_types(ns) == R.recognizer_types(ns)

@@ -82,7 +82,13 @@ def power_of_two_scale(amax: float) -> float:
     """Smallest power of two s with amax / s <= 448 (the E4M3 maximum)."""
     if amax <= 0.0:
         return 1.0
-    return float(2.0 ** math.ceil(math.log2(amax / 448.0)))
+    s = float(2.0 ** math.ceil(math.log2(amax / 448.0)))
+    # log2 of a rounded quotient can land one binade off near amax = 448 * 2**k
+    while amax / s > 448.0:
+        s *= 2.0
+    while amax / (s / 2.0) <= 448.0:
+        s /= 2.0
+    return s
 
 
 @dataclass

@@ -126,9 +126,15 @@ static bool is_pow2_scale(float s) {
   return m == 0.5f;
 }
 
+// Smallest power of two s with amax / s <= 448 (the E4M3 maximum).  log2 of
+// the rounded quotient can land one binade off near amax = 448 * 2^k, so the
+// estimate is corrected against the definition.
 static float pow2_scale_for(float amax) {
   if (!(amax > 0.f)) return 1.f;
-  return ldexpf(1.f, (int)ceil(log2((double)amax / 448.0)));
+  int e = (int)ceil(log2((double)amax / 448.0));
+  while ((double)amax / ldexp(1.0, e) > 448.0) ++e;
+  while ((double)amax / ldexp(1.0, e - 1) <= 448.0) --e;
+  return ldexpf(1.f, e);
 }
 
 static size_t elem_size(ElemType t) { return t == ET_F32 ? 4 : (t == ET_BF16 ? 2 : 1); }

@@ -219,7 +219,7 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
 
 /* ------------------------------------------------------------------------
  * Pattern recognizers and overlap resolution (Sec. II stage 2 pairs the NER
- * model with regular-expression recognizers; Sec. V shows the cost of
+ * model with regular-expression recognizers; Sec. IV-B and App. D show the cost of
  * overlapping detections that are not merged: truncated entities and extra
  * pseudonyms)
  * ------------------------------------------------------------------------
@@ -272,8 +272,8 @@ anon_status recognize_spans(const uint8_t* d_text, const int64_t* d_cu_bytes, in
 
 /* ------------------------------------------------------------------------
  * Schema-aware whole-field spans, no NER (the paper's configuration that maps
- * named fields straight to pseudonyms, bypassing inference: Sec. II; Sec. V,
- * Table VI with and without it)
+ * named fields straight to pseudonyms, bypassing inference: Sec. II; Sec. IV-A;
+ * App. C, Table VI with and without it)
  * ------------------------------------------------------------------------
  * A line is a maximal run of bytes without '\n' inside one record.  It holds
  * a field if its first ':' is directly followed by ' '; the name is the bytes

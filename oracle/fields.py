@@ -2,7 +2,7 @@
 
 The paper's schema-aware configuration maps named fields straight to
 pseudonyms, bypassing inference; it is the paper's largest speedup (Sec. II;
-Sec. V and Table VI, D2 with and without the configuration).  Reading taken
+Sec. IV-A and App. C, Table VI, D2 with and without the configuration).  Reading taken
 here (the GPU path takes the same), for ``Field: value`` records:
 
 * a line is a maximal run of bytes without ``\\n``;

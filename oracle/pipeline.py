@@ -47,9 +47,12 @@ def ner(W, cfg, ids, cu_seqlens, prec=None, window: int = 0, stride: int = 0):
 
 def run(W, cfg, batch, key: bytes, slug_len: int, prec=None, window: int = 0, stride: int = 0,
         labels_override=None) -> OracleResult:
-    z, labels, margin = ner(W, cfg, batch.ids, batch.cu_seqlens, prec, window, stride)
+    """The whole path; with ``labels_override`` the NER stage is skipped and
+    the given labels are decoded and substituted (logits and margins None)."""
     if labels_override is not None:
-        labels = labels_override
+        z, labels, margin = None, np.asarray(labels_override), None
+    else:
+        z, labels, margin = ner(W, cfg, batch.ids, batch.cu_seqlens, prec, window, stride)
     sp = spans_mod.bio_decode(labels, batch.tok_off, batch.cu_seqlens, cfg.n_types)
     outs = pseudonym.pseudonymize_batch(batch.text, batch.cu_bytes, sp, batch.n_records,
                                         batch.type_names, key, slug_len)

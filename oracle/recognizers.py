@@ -5,8 +5,8 @@ recognizers for IPv4/IPv6, URLs, hostnames, hashes, CVE/CPE ids and more
 (Sec. II, stage 2), but prints none of the patterns.  It also reports what a
 missing overlap-resolution layer costs: independent detectors that find
 overlapping spans truncate entities or emit extra pseudonyms, and a single
-leaked occurrence is enough to re-identify (Sec. V, accuracy results and
-false negatives).
+leaked occurrence is enough to re-identify (Sec. IV-B and App. D, accuracy
+results and false negatives).
 
 Readings taken here (the GPU path takes the same):
 

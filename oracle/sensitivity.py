@@ -39,14 +39,33 @@ EPS = 1e-7
 
 
 class _Perturbed(encoder.Precision):
+    """The reduced-precision reading with every value that the GPU forms in
+    FP32 and then rounds to bf16 (stored activations, attention
+    probabilities) perturbed by a relative ``eps`` first.  FP8 GEMM inputs
+    are quantised from values already rounded to bf16, exactly on both
+    sides, so they are not perturbed again."""
+
     def __init__(self, mode, eps, seed, act_scales=None):
         super().__init__(mode, act_scales or [])
         self.rng = np.random.default_rng(seed)
         self.eps = eps
 
-    def store(self, x):
+    def _jitter(self, x):
         x = np.asarray(x, dtype=np.float64)
-        return round_bf16(x * (1.0 + self.eps * self.rng.standard_normal(x.shape)))
+        return x * (1.0 + self.eps * self.rng.standard_normal(x.shape))
+
+    def store(self, x):
+        return round_bf16(self._jitter(x))
+
+    def probs(self, p):
+        return round_bf16(self._jitter(p))
+
+
+def perturbed_forward(W, cfg, ids, cu_seqlens, mode: str, seed: int, act_scales=None, eps: float = EPS,
+                      window: int = 0, stride: int = 0):
+    """Logits, labels and margins of the perturbed reading (one seed)."""
+    from oracle import pipeline as opipe
+    return opipe.ner(W, cfg, ids, cu_seqlens, _Perturbed(mode, eps, seed, act_scales), window, stride)
 
 
 def measure(name: str) -> dict:

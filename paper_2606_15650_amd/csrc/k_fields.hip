@@ -1,6 +1,6 @@
 // Schema-aware whole-field spans without NER: the paper's configuration that
 // maps named fields straight to pseudonyms and bypasses inference (Sec. II;
-// Sec. V, Table VI with and without the configuration).
+// Sec. IV-A; App. C, Table VI with and without the configuration).
 //
 // Records are "Field: value" lines.  A line (a maximal run of bytes without
 // '\n', never crossing a record boundary) holds a field if its first ':' is

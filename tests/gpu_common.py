@@ -1,6 +1,8 @@
 """Shared helpers of the GPU tests: model/cache construction and comparisons."""
 from __future__ import annotations
 
+import json
+import os
 import sys
 
 import numpy as np
@@ -11,17 +13,23 @@ from synth.configs import ModelConfig
 MARGIN = 1e-2        # labels must agree where the reference margin exceeds this
 FP32_LOGIT_RTOL = 1e-4
 
-# Reduced precision: (max logit deviation from the rounding oracle, label margin).
-# Two evaluations within d per logit can only disagree where the top-2 margin
-# is below 2d.  At 2 layers the deviation stays near 1e-3, so the 1e-2 margin
-# holds.  At 12 layers the oracle itself, perturbed by 1e-7 before each bf16
-# rounding, moves by up to 0.017 (tests/golden/sensitivity_base_bf16.json):
-# no bf16 implementation can be held closer, so the bound is 0.03 and the
-# label margin 0.06; agreement above 1e-2 is still measured and reported.
-# At 24 layers with FP8 GEMM inputs the same probe moves the logits by up to
-# 0.21 (tests/golden/sensitivity_large_fp8.json): bound 0.3, margin 0.6.
-REDUCED_GATE = {("bf16", 2): (5e-3, 1e-2), ("fp8", 2): (5e-3, 1e-2), ("bf16", 12): (3e-2, 6e-2),
-                ("fp8", 24): (3e-1, 6e-1)}
+# Reduced precision: the largest logit deviation from the rounding oracle.
+# At 2 layers the deviation stays near 1e-3.  Deeper models are held to twice
+# the spread the oracle itself shows when every value it rounds to bf16 moves
+# by 1e-7 first (the size of FP32 summation differences): no bf16 evaluation
+# can be held closer.  The spreads are measured by oracle/sensitivity.py on
+# the base (12-layer BF16) and large (24-layer FP8) models.  Labels are held
+# to the oracle wherever its margin exceeds 1e-2 at every depth
+# (reduced_label_gate).
+def _probe_bound(name: str) -> float:
+    with open(os.path.join(GOLDEN, f"sensitivity_{name}.json")) as f:
+        return 2.0 * json.load(f)["perturbed_vs_rounding_oracle"]["max"]
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LOGIT_BOUND = {("bf16", 2): 5e-3, ("fp8", 2): 5e-3, ("bf16", 12): _probe_bound("base_bf16"),
+               ("fp8", 24): _probe_bound("large_fp8")}
+PERTURB_SEEDS = (1, 2, 3)
 
 
 def say(*a):
@@ -55,3 +63,35 @@ def confident_labels_agree(lab_gpu, lab_ref, margin_ref):
 
 def confident_records(margin_ref: np.ndarray, cu: np.ndarray) -> list[int]:
     return [b for b in range(len(cu) - 1) if (margin_ref[cu[b]:cu[b + 1]] > MARGIN).all()]
+
+
+def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
+    """Reduced-precision labels against the rounding oracle (zq, lq, mq).
+
+    Every token whose oracle margin exceeds 1e-2 must carry the oracle's
+    label, except a token shown ambiguous on its own: the oracle perturbed by
+    1e-7 before each bf16 rounding (``perturbed(seed)`` -> logits, labels,
+    margins on the same tokens; what FP32 accumulation amounts to) gives the
+    GPU's label there for some seed, or that seed's margin at the token is
+    below the seed's own largest logit deviation from the oracle.  The number
+    of accepted tokens is printed, and may not exceed three times (at least
+    two) the number of labels above 1e-2 that the perturbed oracle itself
+    flips.  Returns that number."""
+    conf = mq > MARGIN
+    bad = np.nonzero(conf & (lab != lq))[0]
+    accepted, own_flips = [], 0
+    if len(bad):
+        runs = [perturbed(s) for s in seeds]
+        for zn, ln, mn in runs:
+            own_flips = max(own_flips, int((conf & (ln != lq)).sum()))
+        for t in bad:
+            for zn, ln, mn in runs:
+                if ln[t] == lab[t] or mn[t] < np.abs(zn - zq).max():
+                    accepted.append(int(t))
+                    break
+    rejected = sorted(set(bad.tolist()) - set(accepted))
+    say(f"  label gate: {int(conf.sum())} tokens above margin 1e-2, {len(bad)} differ, "
+        f"{len(accepted)} accepted as ambiguous (perturbed oracle flips {own_flips})")
+    assert not rejected, f"labels differ above margin 1e-2 at tokens {rejected[:20]} (margins {mq[rejected[:20]]})"
+    assert len(accepted) <= max(2, 3 * own_flips), (len(accepted), own_flips)
+    return len(accepted)

@@ -362,15 +362,28 @@ anon_status pseudonymize(anon_pcache* cache, const uint8_t* d_text, const int64_
 /* ------------------------------------------------------------------------
  * Serving loop: continuous batching of record batches (submit / poll)
  * ------------------------------------------------------------------------
- * A server thread admits queued requests while their activation footprint
- * fits `hbm_budget_bytes` and a stream slot is free, packs them into
- * micro-batches of at most `max_batch_tokens` tokens, runs NER, span
- * decoding and substitution on one of `n_streams` streams, and copies the
- * results back.  Requests that arrive while others run are admitted as soon
- * as budget and a slot free up.  A request's result does not depend on the
- * requests it was batched with. */
+ * anon_submit checks a request (record lengths in [1, max_pos], token ids in
+ * the vocabulary, token byte ranges ordered, disjoint and inside their record,
+ * at most max_request_tokens tokens and 64 text bytes per token: ANON_EINVAL
+ * otherwise), copies it and queues it.  A server thread takes queued requests
+ * in arrival order into micro-batches of at most `max_batch_tokens` tokens and
+ * runs NER, span decoding and substitution on one of `n_streams` streams.
+ * Device memory is one activation arena of min(hbm_budget_bytes, what
+ * n_streams full micro-batches use) bytes, allocated at start; each
+ * micro-batch takes exactly its own footprint (inputs, outputs and the three
+ * stages' workspaces) from it, so requests are admitted while their footprint
+ * fits the budget left and a slot is free.  Requests that arrive while others
+ * run are admitted as soon as budget and a slot free up.  A request's result
+ * does not depend on the requests it was batched with.  Results come back
+ * through events the thread only queries (it never waits on a stream).
+ * Start fails (ANON_ENOMEM) when the budget cannot hold the largest request
+ * anon_submit accepts, so every accepted request can run; the scheduler
+ * still refuses (ANON_ECAPACITY) any request whose footprint alone exceeds
+ * the arena.  A finished request's status is ANON_EDATA when its
+ * micro-batch raised a device-data error bit (each micro-batch has its own
+ * error word; requests that pass anon_submit's checks do not raise any). */
 typedef struct {
-  int64_t hbm_budget_bytes;   /* activation budget (e.g. 64 GiB)          */
+  int64_t hbm_budget_bytes;   /* activation budget (e.g. 64 GiB)           */
   int32_t max_batch_tokens;   /* tokens per micro-batch                    */
   int32_t n_streams;          /* micro-batches in flight (1..8)            */
   int32_t max_queue;          /* queued requests before anon_submit EBUSY  */
@@ -406,6 +419,15 @@ anon_status anon_submit(anon_server* server, const anon_request* req, uint64_t* 
 /* ANON_PENDING while running; ANON_OK once `out` is filled. */
 anon_status anon_poll(anon_server* server, uint64_t ticket, anon_result* out);
 anon_status anon_release(anon_server* server, uint64_t ticket);
+/* Counters since start: the arena size, the most arena bytes in use at once,
+ * micro-batches launched and the most micro-batches in flight at once. */
+typedef struct {
+  int64_t arena_bytes;
+  int64_t peak_arena_bytes;
+  int64_t micro_batches;
+  int32_t max_concurrent;
+} anon_server_counters;
+anon_status anon_server_stats(anon_server* server, anon_server_counters* out);
 /* Finishes in-flight work, fails queued requests, joins the thread. */
 anon_status anon_server_stop(anon_server* server);
 

@@ -53,6 +53,11 @@ class RequestC(C.Structure):
                 ("cu_bytes", C.POINTER(C.c_int64))]
 
 
+class ServerCountersC(C.Structure):
+    _fields_ = [("arena_bytes", C.c_int64), ("peak_arena_bytes", C.c_int64), ("micro_batches", C.c_int64),
+                ("max_concurrent", C.c_int32)]
+
+
 class ResultC(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_records", C.c_int32), ("n_tokens", C.c_int32), ("n_spans", C.c_int32),
                 ("out", C.POINTER(C.c_uint8)), ("cu_out", C.POINTER(C.c_int64)), ("labels", C.POINTER(C.c_uint8)),
@@ -97,6 +102,7 @@ _SIGS = {
     "anon_poll": ([vp, u64, C.POINTER(ResultC)], i32),
     "anon_release": ([vp, u64], i32),
     "anon_server_stop": ([vp], i32),
+    "anon_server_stats": ([vp, C.POINTER(ServerCountersC)], i32),
     "anon_autotune": ([vp, i32, vp, sz, vp, C.POINTER(i32), C.POINTER(C.c_float), i32], i32),
     "anon_model_set_tiles": ([vp, C.POINTER(i32)], i32),
     "anon_model_set_tile_groups": ([vp, C.POINTER(i32)], i32),
@@ -479,6 +485,14 @@ class Server:
 
     def release(self, ticket: int):
         _check("anon_release", lib().anon_release(self.handle, ticket))
+
+    def stats(self) -> dict:
+        """anon_server_stats: arena size, peak arena bytes in use, micro-batches
+        launched, most micro-batches in flight at once."""
+        c = ServerCountersC()
+        _check("anon_server_stats", lib().anon_server_stats(self.handle, C.byref(c)))
+        return {"arena_bytes": c.arena_bytes, "peak_arena_bytes": c.peak_arena_bytes,
+                "micro_batches": c.micro_batches, "max_concurrent": c.max_concurrent}
 
     def stop(self):
         if getattr(self, "handle", None):

@@ -41,8 +41,12 @@ __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bit) {
   if (err) atomicOr(err, bit);
 }
 
-// Address of the current device's error word (allocated once per device).
+// Address of the current device's error word (allocated once per device),
+// or the word set for the calling thread by set_thread_error_word.
 uint32_t* error_word_ptr();
+// Route the error bits of this thread's later launches to `w` (device
+// memory, the caller's); nullptr restores the per-device word.
+void set_thread_error_word(uint32_t* w);
 
 constexpr int kWave = 64;
 

@@ -27,7 +27,13 @@ void clear_error() { t_last_error.clear(); }
 static std::mutex g_err_mu;
 static uint32_t* g_err_words[64] = {nullptr};
 
+// A caller that wants the errors of its own launches apart (the server, per
+// micro-batch) points this thread's launches at another word for a while.
+static thread_local uint32_t* t_err_override = nullptr;
+void set_thread_error_word(uint32_t* w) { t_err_override = w; }
+
 uint32_t* error_word_ptr() {
+  if (t_err_override) return t_err_override;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   std::lock_guard<std::mutex> lk(g_err_mu);

@@ -90,3 +90,53 @@ def test_mapping_export_after_three_calls(torch_dev):
     _pseudo(B, calls[1][1], cache)
     rows = cache.export()
     assert rows and all(r["first_seen"] == 1 and r["last_seen"] == 1 for r in rows)
+
+
+def test_many_duplicate_inserts_of_one_entity_in_one_call(torch_dev):
+    """20,000 spans of one entity (plus a few others) in one call: every probe
+    of the first call races to insert the same key.  The output equals the
+    oracle's, the counters add up, the table ends with one row for the
+    entity after the export merges racing inserts, and a second call is
+    served from the table."""
+    from synth.records import RecordBatch
+    hot = b"10.20.30.40"
+    others = [b"db01.corp", b"CVE-2021-44228", b"alice@example.org"]
+    texts, spans = [], []
+    for r in range(2000):
+        parts, sp = [], []
+        pos = 0
+        for k in range(10):
+            ent = hot if (k + r) % 11 else others[(k + r) % 3]
+            pre = b"host " if k else b""
+            parts += [pre, ent, b" "]
+            pos += len(pre)
+            sp.append((r, 1 if ent == hot else 2, pos, pos + len(ent)))
+            pos += len(ent) + 1
+        texts.append(b"".join(parts))
+        spans += sp
+    text = b"".join(texts)
+    cu_bytes = np.concatenate([[0], np.cumsum([len(t) for t in texts])]).astype(np.int64)
+    # one token per record (the pseudonymizer reads text and spans only)
+    rb = RecordBatch(text, cu_bytes, np.zeros(2000, np.int32), np.zeros((2000, 2), np.int32),
+                     np.arange(2001, dtype=np.int32), np.zeros(2000, np.uint8), np.zeros((0, 4), np.int64),
+                     ["IP_ADDRESS", "HOSTNAME", "CVE_ID", "EMAIL_ADDRESS"])
+    spans = np.array(spans, np.int64)
+    n_hot = int((spans[:, 1] == 1).sum())
+    say(f"[pcache] {len(spans)} spans, {n_hot} of them the same entity, one call")
+    cache = make_cache(rb.type_names, capacity=1 << 12)
+    got = _pseudo(rb, spans, cache)
+    want = ops.pseudonymize_batch(rb.text, rb.cu_bytes, spans, rb.n_records, rb.type_names, synth.make_key(0), 10)
+    assert got == want
+    st = cache.stats()
+    say(f"  first call: {st}")
+    assert st["lookups"] == len(spans)
+    assert 4 <= st["entries"] <= st["lookups"] - st["hits"]
+    rows = cache.export()
+    hot_rows = [r for r in rows if r["original"] == hot]
+    assert len(hot_rows) == 1 and hot_rows[0]["entity_type"] == "IP_ADDRESS"
+    assert sorted(r["original"] for r in rows) == sorted([hot] + others)
+    got2 = _pseudo(rb, spans, cache)
+    assert got2 == want
+    st2 = cache.stats()
+    assert st2["hits"] - st["hits"] == len(spans)
+    cache.close()

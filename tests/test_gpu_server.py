@@ -106,6 +106,59 @@ def test_bad_requests_are_rejected(server):
         _submit(sv, big)
     with pytest.raises(api.AnonError):
         sv.poll(987654321)
+    # token byte ranges that overlap, or run past their record, are refused
+    # before anything reaches the GPU (a bad range would make an entity span
+    # leave its record or overlap another, and its bytes would stay in clear)
+    bad_off = rb.tok_off.copy()
+    bad_off[3, 0] = bad_off[2, 0]
+    with pytest.raises(api.AnonError):
+        sv.submit(rb.ids, rb.cu_seqlens, bad_off, rb.text, rb.cu_bytes)
+    bad_off = rb.tok_off.copy()
+    bad_off[int(rb.cu_seqlens[1]) - 1, 1] = int(rb.cu_bytes[1] - rb.cu_bytes[0]) + 1
+    with pytest.raises(api.AnonError):
+        sv.submit(rb.ids, rb.cu_seqlens, bad_off, rb.text, rb.cu_bytes)
+    bad_off = rb.tok_off.copy()
+    bad_off[0] = (5, 2)
+    with pytest.raises(api.AnonError):
+        sv.submit(rb.ids, rb.cu_seqlens, bad_off, rb.text, rb.cu_bytes)
+    # the server still serves after the refusals
+    r = _wait(sv, _submit(sv, rb))
+    assert r["status"] == 0
+
+
+def test_admission_by_activation_budget():
+    """With a budget that holds one full micro-batch (and not two), micro-batches
+    never run concurrently although three slots are free, the arena in use
+    never exceeds the budget, and every result equals the one a roomy server
+    gives."""
+    from paper_2606_15650_amd import api
+    W, m = make_model(TINY, "bf16", 0)
+    cache = make_cache(synth.TYPE_NAMES_9)
+    # requests of 960 tokens: one per 1024-token micro-batch, each taking
+    # most of a full micro-batch's footprint, so two never fit 1.5 of them
+    rb = synth.generate_records(96, np.full(96, 120), 4, TINY.vocab, 46)
+    reqs = _requests(rb, [8] * 12)
+    roomy = api.Server(m, cache, hbm_budget_bytes=8 << 30, max_batch_tokens=1024, n_streams=3, max_queue=256)
+    full = roomy.stats()["arena_bytes"] // 3  # one full micro-batch
+    ref = [_wait(roomy, _submit(roomy, q)) for q in reqs]
+    st_roomy = roomy.stats()
+    roomy.stop()
+    tight = api.Server(m, cache, hbm_budget_bytes=full + full // 2, max_batch_tokens=1024, n_streams=3,
+                       max_queue=256)
+    tickets = [_submit(tight, q) for q in reqs]
+    got = [_wait(tight, t) for t in tickets]
+    st = tight.stats()
+    tight.stop()
+    say(f"[server] roomy {st_roomy}; tight {st}")
+    assert st["arena_bytes"] <= full + full // 2
+    assert st["peak_arena_bytes"] <= st["arena_bytes"]
+    assert st["max_concurrent"] == 1
+    for a, b in zip(ref, got):
+        assert b["status"] == 0
+        np.testing.assert_array_equal(a["labels"], b["labels"])
+        assert a["out"] == b["out"]
+    m.close()
+    cache.close()
 
 
 def test_stop_with_work_in_flight_finishes_cleanly():

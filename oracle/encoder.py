@@ -65,11 +65,12 @@ def attention(q: np.ndarray, k: np.ndarray, v: np.ndarray, round_p=None) -> np.n
     sum (the GPU's order).
     """
     d = q.shape[-1]
-    s = np.einsum("qhd,khd->hqk", q, k) / math.sqrt(d)
+    qh, kh, vh = (np.ascontiguousarray(t.transpose(1, 0, 2)) for t in (q, k, v))   # [H, L, d]
+    s = qh @ kh.transpose(0, 2, 1) / math.sqrt(d)                                   # [H, Lq, Lk]
     p = np.exp(s - s.max(axis=-1, keepdims=True))
     l = p.sum(axis=-1, keepdims=True)
     pv = p if round_p is None else round_p(p)
-    o = np.einsum("hqk,khd->hqd", pv, v) / l
+    o = (pv @ vh) / l
     return o.transpose(1, 0, 2)
 
 

@@ -2,7 +2,8 @@
 
 These model the GPU's rounding points for the reduced-precision reading of the
 encoder (the paper states no precision; see oracle.encoder).  Both are plain
-round-to-nearest-even on the significand, written out with frexp/ldexp.
+round-to-nearest-even on the significand: bf16 on the float64 encoding, E4M3
+with frexp/ldexp.
 """
 from __future__ import annotations
 
@@ -12,12 +13,21 @@ import numpy as np
 def round_bf16(x) -> np.ndarray:
     """Round to bfloat16 (8 significant bits, 8-bit exponent), ties to even.
 
-    Values are kept as float64.  Overflow and bf16 subnormals do not occur in
-    this model's activations and are not modelled.
+    Values are kept as float64.  A float64 carries 53 significant bits, so
+    keeping 8 drops the low 45 bits of its encoding: add half a unit of the
+    kept last place (minus one when that place is even, so that an exact tie
+    goes to the even neighbour) and clear the dropped bits.  A carry out of the
+    significand moves into the exponent, which is the correct result.  Overflow
+    and bf16 subnormals do not occur in this model's activations and are not
+    modelled.
     """
-    x = np.asarray(x, dtype=np.float64)
-    m, e = np.frexp(x)                       # x = m * 2**e, 0.5 <= |m| < 1
-    return np.ldexp(np.round(m * 256.0) / 256.0, e)
+    u = np.array(x, dtype=np.float64).view(np.uint64)      # a copy, rounded in place
+    r = u >> np.uint64(45)
+    r &= np.uint64(1)                                      # last kept bit
+    r += np.uint64((1 << 44) - 1)                          # half a unit, less one
+    u += r
+    u &= np.uint64(0xFFFFFFFFFFFFFFFF ^ ((1 << 45) - 1))   # clear the 45 dropped bits
+    return u.view(np.float64)
 
 
 E4M3_MAX = 448.0

@@ -61,6 +61,11 @@ class _Perturbed(encoder.Precision):
         return round_bf16(self._jitter(p))
 
 
+def perturbed_precision(mode: str, seed: int, act_scales=None, eps: float = EPS) -> encoder.Precision:
+    """The perturbed reading as a Precision (its own random stream)."""
+    return _Perturbed(mode, eps, seed, act_scales)
+
+
 def perturbed_forward(W, cfg, ids, cu_seqlens, mode: str, seed: int, act_scales=None, eps: float = EPS,
                       window: int = 0, stride: int = 0):
     """Logits, labels and margins of the perturbed reading (one seed)."""

@@ -32,6 +32,51 @@ LOGIT_BOUND = {("bf16", 2): 5e-3, ("fp8", 2): 5e-3, ("bf16", 12): _probe_bound("
 PERTURB_SEEDS = (1, 2, 3)
 
 
+def oracle_ner(W, cfg, ids, cu_seqlens, make_prec=None, window: int = 0, stride: int = 0, workers: int | None = None):
+    """The oracle's NER (logits, labels, margins) over a packed batch, with its
+    records split into contiguous groups of about equal token counts that run
+    in parallel threads (numpy releases the GIL in its array work).  Each
+    group is a packed batch of its own: the oracle's result for a record does
+    not depend on its batch-mates (pinned on the CPU).  ``make_prec(g)`` gives
+    group g its Precision (a fresh one per group, so that a stateful reading
+    such as the perturbed one draws from its own stream)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pipeline as opipe
+    cu = np.asarray(cu_seqlens, dtype=np.int64)
+    ids = np.asarray(ids)
+    B = len(cu) - 1
+    make_prec = make_prec or (lambda g: None)
+    workers = workers or min(16, os.cpu_count() or 1)
+    # group boundaries by token count; every token weighs at least its
+    # record's share of attention (long records cost more per token)
+    L = np.diff(cu).astype(np.float64)
+    cost = np.cumsum(L * (1.0 + L / 256.0))
+    n_groups = max(1, min(B, 2 * workers))
+    bounds = [0]
+    for g in range(1, n_groups):
+        r = int(np.searchsorted(cost, cost[-1] * g / n_groups)) + 1
+        if bounds[-1] < r < B:
+            bounds.append(r)
+    bounds.append(B)
+
+    def run(g):
+        a, b = bounds[g], bounds[g + 1]
+        sub_cu = cu[a:b + 1] - cu[a]
+        return opipe.ner(W, cfg, ids[cu[a]:cu[b]], sub_cu, make_prec(g), window, stride)
+
+    if B == 0:
+        return opipe.ner(W, cfg, ids, cu, make_prec(0), window, stride)
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(run, range(len(bounds) - 1)))
+    z = np.concatenate([p[0] for p in parts])
+    lab = np.concatenate([p[1] for p in parts])
+    mg = np.concatenate([p[2] for p in parts])
+    return z, lab, mg
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

@@ -16,7 +16,7 @@ from oracle import encoder, pipeline as opipe, pseudonym as ops, spans as ospans
 from synth.configs import TINY, BASE, LARGE, ModelConfig
 from oracle import sensitivity
 from tests.gpu_common import (MARGIN, FP32_LOGIT_RTOL, LOGIT_BOUND, confident_labels_agree, confident_records,
-                              logit_rel_err, make_cache, make_model, reduced_label_gate, say)
+                              logit_rel_err, make_cache, make_model, oracle_ner, reduced_label_gate, say)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -378,15 +378,20 @@ def test_base_bf16_small_batch_vs_rounding_oracle(torch_dev):
     W, m = make_model(BASE, "bf16", 0, o_target=0.92)
     say(f"[base bf16] T={rb.n_tokens}")
     lab, z, mg = _run_ner(m, rb)
-    zq, lq, mq = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens, encoder.Precision("bf16"))
-    zp, lp, mp = encoder.forward(W, BASE, rb.ids, rb.cu_seqlens)
+    zq, lq, mq = oracle_ner(W, BASE, rb.ids, rb.cu_seqlens, lambda g: encoder.Precision("bf16"))
+    zp, lp, mp = oracle_ner(W, BASE, rb.ids, rb.cu_seqlens)
     dev_q, dev_p = np.abs(z - zq).max(), np.abs(z - zp).max()
     bound = LOGIT_BOUND[("bf16", BASE.n_layers)]
     say(f"  max |z-zq| {dev_q:.3e}  max |z-zpure| {dev_p:.3e}  O-rate {(lab == 0).mean():.3f}")
     assert dev_q < bound and dev_p < bound
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: sensitivity.perturbed_forward(W, BASE, rb.ids, rb.cu_seqlens,
-                                                                                 "bf16", sd))
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, BASE, rb, "bf16", sd))
     m.close()
+
+
+def _perturbed(W, cfg, rb, mode, seed, scales=None):
+    """The perturbed oracle on a batch (each thread group draws its own stream)."""
+    return oracle_ner(W, cfg, rb.ids, rb.cu_seqlens,
+                      lambda g: sensitivity.perturbed_precision(mode, 1000 * seed + g, scales))
 
 
 def _class_sample(L: np.ndarray, per_class: int, seed: int) -> list[int]:
@@ -427,13 +432,12 @@ def test_base_bf16_full_batch_sampled_records(torch_dev):
     sample = _class_sample(np.diff(rb.cu_seqlens), 16, 7)
     sub = rb.subset(sample)
     say(f"  {len(sample)} records, {sub.n_tokens} tokens, lengths {np.diff(sub.cu_seqlens).tolist()}: oracle")
-    zq, lq, mq = encoder.forward(W, BASE, sub.ids, sub.cu_seqlens, encoder.Precision("bf16"))
+    zq, lq, mq = oracle_ner(W, BASE, sub.ids, sub.cu_seqlens, lambda g: encoder.Precision("bf16"))
     rows = np.concatenate([np.arange(rb.cu_seqlens[r], rb.cu_seqlens[r + 1]) for r in sample])
     dev = np.abs(z_full[rows] - zq).max()
     say(f"  max |z - z_bf16oracle| {dev:.3e} (bound {LOGIT_BOUND[('bf16', BASE.n_layers)]})")
     assert dev < LOGIT_BOUND[("bf16", BASE.n_layers)]
-    reduced_label_gate(lab[rows], zq, lq, mq,
-                       lambda sd: sensitivity.perturbed_forward(W, BASE, sub.ids, sub.cu_seqlens, "bf16", sd))
+    reduced_label_gate(lab[rows], zq, lq, mq, lambda sd: _perturbed(W, BASE, sub, "bf16", sd))
     key = synth.make_key(0)
     res = opipe.run(W, BASE, sub, key, 10, labels_override=lab[rows])
     for i, r in enumerate(sample):
@@ -580,13 +584,12 @@ def test_large_fp8_records_at_every_attention_class_bound(torch_dev):
     lab, z, mg = _run_ner(m, rb)
     bound = LOGIT_BOUND[("fp8", LARGE.n_layers)]
     sc = _fp8_scales("large_fp8")
-    zq, lq, mq = encoder.forward(W, LARGE, rb.ids, rb.cu_seqlens, encoder.Precision("fp8", act_scales=sc))
+    zq, lq, mq = oracle_ner(W, LARGE, rb.ids, rb.cu_seqlens, lambda g: encoder.Precision("fp8", act_scales=sc))
     for r, n in enumerate(lens):
         a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
         say(f"  record {r} ({n} tokens): max |z - z_oracle| {np.abs(z[a:b] - zq[a:b]).max():.3e}")
     assert np.abs(z - zq).max() < bound
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: sensitivity.perturbed_forward(W, LARGE, rb.ids, rb.cu_seqlens,
-                                                                                 "fp8", sd, act_scales=sc))
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, LARGE, rb, "fp8", sd, sc))
     for r in range(len(FP8_CLASS_LENGTHS)):
         a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
         l1, z1, _ = _run_ner(m, rb.subset([r]))
@@ -609,13 +612,12 @@ def test_fp8_attention_length_classes_two_layers(torch_dev):
     rb = synth.generate_records(len(lens), np.array(lens), 4, cfg.vocab, 12)
     say(f"[fp8 classes] lengths {lens}")
     lab, z, mg = _run_ner(m, rb)
-    zq, lq, mq = encoder.forward(W, cfg, rb.ids, rb.cu_seqlens, encoder.Precision("fp8", act_scales=sc))
+    zq, lq, mq = oracle_ner(W, cfg, rb.ids, rb.cu_seqlens, lambda g: encoder.Precision("fp8", act_scales=sc))
     err = np.abs(z - zq).max()
     # the bar: twice the oracle's own spread on this case when perturbed by
     # 1e-7 before each bf16 rounding (about 5e-3 here: wider and longer
     # records than the tiny model's)
-    runs = {sd: sensitivity.perturbed_forward(W, cfg, rb.ids, rb.cu_seqlens, "fp8", sd, act_scales=sc)
-            for sd in (1, 2, 3)}
+    runs = {sd: _perturbed(W, cfg, rb, "fp8", sd, sc) for sd in (1, 2, 3)}
     spread = max(np.abs(r[0] - zq).max() for r in runs.values())
     say(f"  max |z - z_fp8oracle| {err:.3e}; perturbed oracle spread {spread:.3e}")
     assert err < 2 * spread

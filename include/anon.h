@@ -217,6 +217,20 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
                          int32_t T, int32_t n_types, anon_span* d_spans, int32_t span_cap, int32_t* d_cu_spans,
                          void* d_workspace, size_t ws_bytes, void* stream);
 
+/* decode_spans without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Its flag, offset and scan buffers are a device
+ * array of the library of about 8.4 MB, one copy per GPU held until the
+ * process ends; nothing is allocated.  T must be at most
+ * ANON_NOALLOC_MAX_TOKENS (ANON_ECAPACITY otherwise, before any launch); the
+ * other arguments and the outputs are those of decode_spans.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (two streams,
+ * two threads) race and must be ordered by the caller. */
+#define ANON_NOALLOC_MAX_TOKENS (1 << 20)
+anon_status decode_spans_noalloc(const uint8_t* d_labels, const int32_t* d_tok_off, const int32_t* d_cu_seqlens,
+                                 int32_t B, int32_t T, int32_t n_types, anon_span* d_spans, int32_t span_cap,
+                                 int32_t* d_cu_spans, void* stream);
+
 /* ------------------------------------------------------------------------
  * Pattern recognizers and overlap resolution (Sec. II stage 2 pairs the NER
  * model with regular-expression recognizers; Sec. IV-B and App. D show the cost of

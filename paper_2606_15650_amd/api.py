@@ -83,6 +83,7 @@ _SIGS = {
     "ner_forward_windowed": ([vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
     "decode_spans": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+    "decode_spans_noalloc": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp], i32),
     "anon_recognize_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
     "anon_field_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
     "field_spans": ([vp, vp, i32, i64, C.POINTER(C.c_char_p), C.POINTER(i32), i32, i32, vp, i32, vp, vp, sz, vp],
@@ -294,6 +295,17 @@ def decode_spans(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int
     _check("decode_spans", lib().decode_spans(ptr(d_labels), ptr(d_tok_off), ptr(d_cu_seqlens), B, T, n_types,
                                               ptr(d_spans), span_cap, ptr(d_cu_spans), ptr(d_workspace), ws_bytes,
                                               stream_handle(stream)))
+
+
+NOALLOC_MAX_TOKENS = 1 << 20  # ANON_NOALLOC_MAX_TOKENS
+
+
+def decode_spans_noalloc(d_labels, d_tok_off, d_cu_seqlens, B: int, T: int, n_types: int, d_spans, span_cap: int,
+                         d_cu_spans, stream=None):
+    """decode_spans with the library's per-device scratch array (no workspace, no allocation)."""
+    _check("decode_spans_noalloc", lib().decode_spans_noalloc(ptr(d_labels), ptr(d_tok_off), ptr(d_cu_seqlens), B, T,
+                                                              n_types, ptr(d_spans), span_cap, ptr(d_cu_spans),
+                                                              stream_handle(stream)))
 
 
 # Recognizer order of recognize_spans (the type each emits is chosen per call),

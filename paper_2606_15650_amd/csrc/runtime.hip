@@ -32,16 +32,19 @@ static uint32_t* g_err_words[64] = {nullptr};
 static thread_local uint32_t* t_err_override = nullptr;
 void set_thread_error_word(uint32_t* w) { t_err_override = w; }
 
+// The per-device error word is a device array of the library (zero when the
+// code object loads, one copy per GPU), so that no call allocates for it.
+static __device__ __align__(256) uint32_t g_err_dev[64];
+
 uint32_t* error_word_ptr() {
   if (t_err_override) return t_err_override;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
   std::lock_guard<std::mutex> lk(g_err_mu);
   if (!g_err_words[dev]) {
-    uint32_t* p = nullptr;
-    if (hipMalloc(&p, 256) != hipSuccess) return nullptr;
-    if (hipMemset(p, 0, 256) != hipSuccess) return nullptr;
-    g_err_words[dev] = p;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_dev)) != hipSuccess) return nullptr;
+    g_err_words[dev] = (uint32_t*)p;
   }
   return g_err_words[dev];
 }
@@ -889,6 +892,49 @@ anon_status decode_spans(const uint8_t* d_labels, const int32_t* d_tok_off, cons
                    err, s);
   ANON_HIP_CHECK(hipGetLastError());
   return ANON_OK;
+}
+
+// decode_spans_noalloc: the same kernels with their flag, offset and scan
+// buffers in `scratch`, a device array sized for ANON_NOALLOC_MAX_TOKENS
+// tokens.  Host code never passes the array's name to a kernel (that is a
+// host-side stand-in): each device's own address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static constexpr size_t kNoAllocScratchBytes =
+    (size_t)ANON_NOALLOC_MAX_TOKENS * 4 * 2 + ((size_t)ANON_NOALLOC_MAX_TOKENS / 256 + 64) * 8 + 4 * 256;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {nullptr};
+
+static anon_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  ANON_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return set_error(ANON_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(ANON_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ANON_OK;
+}
+
+anon_status decode_spans_noalloc(const uint8_t* d_labels, const int32_t* d_tok_off, const int32_t* d_cu_seqlens,
+                                 int32_t B, int32_t T, int32_t n_types, anon_span* d_spans, int32_t span_cap,
+                                 int32_t* d_cu_spans, void* stream) {
+  clear_error();
+  if (T > ANON_NOALLOC_MAX_TOKENS)
+    return set_error(ANON_ECAPACITY, "decode_spans_noalloc: T = " + std::to_string(T) + " exceeds " +
+                                         std::to_string(ANON_NOALLOC_MAX_TOKENS) + " tokens");
+  if (T < 0) return set_error(ANON_EINVAL, "negative size");
+  void* ws = nullptr;
+  anon_status st = scratch_for_current_device(&ws);
+  if (st != ANON_OK) return st;
+  // the flags and offsets are fully rewritten by every call (no state to clear)
+  return decode_spans(d_labels, d_tok_off, d_cu_seqlens, B, T, n_types, d_spans, span_cap, d_cu_spans, ws,
+                      kNoAllocScratchBytes, stream);
 }
 
 anon_status anon_recognize_workspace_size(int64_t n_bytes, int32_t B, size_t* bytes) {

@@ -75,8 +75,10 @@ def path_flops(cfg, cu: np.ndarray) -> float:
     return cfg.n_layers * (g * T + attention_flops(cu, cfg)) + 2.0 * cfg.hidden * cfg.n_labels * T
 
 
-def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
-    """The FP64 oracle on the first records of the workload, until ~budget_s of CPU work."""
+def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0):
+    """The FP64 oracle on the first records of the workload, until ~budget_s of
+    CPU work.  Returns the baseline entry and the oracle's logits, labels and
+    outputs of the records it ran (the parity leg compares the GPU with them)."""
     from oracle import pipeline as opipe
     try:
         from threadpoolctl import threadpool_info
@@ -85,17 +87,73 @@ def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0) -> dict:
         threads = os.cpu_count() or 1
     tok = 0
     nrec = 0
+    zs, outs = [], []
     t0 = time.perf_counter()
     step = 2
     while nrec < rb.n_records and time.perf_counter() - t0 < budget_s:
         sub = rb.subset(range(nrec, min(nrec + step, rb.n_records)))
-        opipe.run(W, wl.model, sub, key, 10)
+        res = opipe.run(W, wl.model, sub, key, 10)
+        zs.append(res.logits)
+        outs.extend(res.outputs)
         tok += sub.n_tokens
         nrec += sub.n_records
     dt = time.perf_counter() - t0
-    return {"value": tok / dt, "unit": "tokens/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {nrec} records ({tok} tokens) of the {wl.name} workload through the FP64 oracle "
-                      f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
+    entry = {"value": tok / dt, "unit": "tokens/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"first {nrec} records ({tok} tokens) of the {wl.name} workload through the FP64 oracle "
+                       f"(NER, spans, HMAC substitution) in {dt:.1f} s"}
+    return entry, {"nrec": nrec, "z": np.concatenate(zs), "outputs": outs}
+
+
+def parity_leg(wl, rb, W, pure: dict, gpu: dict, scales=None) -> dict:
+    """Logit error and label agreement of the GPU path on the oracle's sample
+    records (part of the CPU baseline leg): against the pure FP64 oracle and,
+    for BF16/FP8, against the oracle that rounds where the GPU stores."""
+    from oracle import encoder
+    MARGIN = 1e-2
+    nrec = pure["nrec"]
+    n = int(rb.cu_seqlens[nrec])
+    zg, lg = gpu["z"][:n].astype(np.float64), gpu["labels"][:n]
+
+    def compare(zr):
+        lr, mr = encoder.argmax_margin(zr)
+        d = np.abs(zg - zr)
+        conf = mr > MARGIN
+        return {"max_abs_logit_err": float(d.max()), "rms_logit_err": float(np.sqrt((d ** 2).mean())),
+                "rel_frobenius": float(np.linalg.norm(zg - zr) / max(np.linalg.norm(zr), 1e-30)),
+                "label_agreement_all": float((lg == lr).mean()),
+                "label_agreement_confident": float((lg[conf] == lr[conf]).mean()) if conf.any() else 1.0,
+                "confident_label_mismatches": int((conf & (lg != lr)).sum()),
+                "tokens_margin_le_1e-2": int((~conf).sum())}
+
+    out = {"records": nrec, "tokens": n, "vs_pure_fp64_oracle": compare(pure["z"])}
+    if wl.precision != "fp32":
+        sub = rb.subset(range(nrec))
+        prec = encoder.Precision(wl.precision, [list(map(float, r)) for r in np.asarray(scales).reshape(-1, 4)]
+                                 if scales is not None else [])
+        t0 = time.perf_counter()
+        zq, lq, mq = encoder.forward(W, wl.model, sub.ids, sub.cu_seqlens, prec)
+        out["vs_rounding_oracle"] = r = compare(zq)
+        r["oracle_s"] = time.perf_counter() - t0
+        # the confident mismatches: ambiguous ones are those where the oracle
+        # perturbed by 1e-7 before each rounding (3 seeds, run on the records
+        # that hold them) also gives the GPU's label or a margin below its own
+        # deviation
+        bad = np.nonzero((mq > MARGIN) & (lg != lq))[0]
+        if len(bad):
+            from oracle import sensitivity
+            recs = sorted(set(int(np.searchsorted(rb.cu_seqlens, t, side="right") - 1) for t in bad))
+            acc = 0
+            for rec in recs:
+                a, b = int(rb.cu_seqlens[rec]), int(rb.cu_seqlens[rec + 1])
+                one = rb.subset([rec])
+                runs = [sensitivity.perturbed_forward(W, wl.model, one.ids, one.cu_seqlens, wl.precision, sd,
+                                                      act_scales=prec.act_scales or None) for sd in (1, 2, 3)]
+                tok = [int(t) - a for t in bad if a <= t < b]
+                acc += len(sensitivity.ambiguous_tokens(lg[a:b], zq[a:b], tok, runs))
+            r["confident_mismatches_ambiguous"] = acc
+            r["confident_mismatches_unexplained"] = int(len(bad) - acc)
+    out["outputs_equal_pure_oracle"] = int(sum(a == b for a, b in zip(gpu["outputs"][:nrec], pure["outputs"])))
+    return out
 
 
 def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, streams: int = 3,
@@ -360,6 +418,8 @@ def main() -> int:
                     help="skip the short serving run (100 req/s) of the default line")
     ap.add_argument("--no-recognizers", action="store_true",
                     help="skip the timings of the recognizer and schema-field paths")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 path on the large workload")
+    ap.add_argument("--fp8-steps", type=int, default=3)
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
@@ -388,209 +448,226 @@ def main() -> int:
 
     import synth
     from paper_2606_15650_amd import api
-    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list
 
-    wl = synth.workload(a.workload)
-    cfg = wl.model
-    t_gen = time.perf_counter()
-    rb = synth.generate_records(wl.n_records, wl.lengths, cfg.n_types, cfg.vocab, wl.seed)
-    W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
-    key = synth.make_key(0)
-    blob = synth.weights_blob(cfg, W)
-    gen_s = time.perf_counter() - t_gen
-    T, B = rb.n_tokens, rb.n_records
-    cu = rb.cu_seqlens.astype(np.int64)
+    def path_bench(wl_name: str, steps: int, warmup: int, extras: bool, fp32: bool, keep_logits: bool) -> dict:
+        """One workload: generate it, time `steps` whole-path steps (the path in
+        the workload's precision), the dominant kernel against its roofline,
+        optionally the recognizer / schema-field / graph timings and the FP32
+        path on the same batch; with keep_logits the GPU logits, labels and
+        outputs of one more step are returned for the parity leg."""
+        wl = synth.workload(wl_name)
+        cfg = wl.model
+        t_gen = time.perf_counter()
+        rb = synth.generate_records(wl.n_records, wl.lengths, cfg.n_types, cfg.vocab, wl.seed)
+        W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
+        key = synth.make_key(0)
+        blob = synth.weights_blob(cfg, W)
+        gen_s = time.perf_counter() - t_gen
+        T, B = rb.n_tokens, rb.n_records
+        cu = rb.cu_seqlens.astype(np.int64)
+        scales = None
+        if wl.precision == "fp8":
+            # static per-tensor activation scales, calibrated once by the oracle
+            with open(os.path.join(ROOT, "tests", "golden", f"fp8_scales_{wl.name}.json")) as f:
+                scales = np.asarray(json.load(f)["scales"], np.float32).reshape(-1)
+        kept = {}
 
-    scales = None
-    if wl.precision == "fp8":
-        # static per-tensor activation scales, calibrated once by the oracle
-        with open(os.path.join(ROOT, "tests", "golden", f"fp8_scales_{wl.name}.json")) as f:
-            scales = np.asarray(json.load(f)["scales"], np.float32).reshape(-1)
+        def run_path(precision: str, steps: int, warmup: int, prof: bool, extras: bool = False):
+            model = api.Model(cfg, blob, precision, act_scales=scales if precision == "fp8" else None)
+            cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
+            pl = Pipeline(model, cache)
+            db = DeviceBatch(rb)
+            stream = torch.cuda.current_stream()
+            tiles, _ = pl.autotune(T, B)
+            groups = model.get_tiles()[1]
+            tiles = [f"{model.tile_configs()[t]}_g{g if g else 'auto'}" for t, g in zip(tiles, groups)]
+            for _ in range(warmup):
+                pl.step(db)
+            torch.cuda.synchronize()
+            classes = ["qkv", "attn", "oproj", "ffn1", "ffn2", "ln", "embed", "cls"]
+            if prof:
+                for k in classes:
+                    api.prof_enable(k, True)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev[0].record(stream)
+            for i in range(steps):
+                pl.step(db)
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+            kern = {}
+            if prof:
+                for k in classes:
+                    kern[k] = api.prof_read(k)
+                    api.prof_enable(k, False)
+            st = cache.stats()
+            if keep_logits and precision == wl.precision:
+                # one more (untimed) pass for the parity leg: logits, labels, outputs
+                _, z, _ = pl.ner(db, logits=True)
+                labels, spans, cu_spans, out, cu_out = pl.step(db)
+                torch.cuda.synchronize()
+                kept["z"] = z[:T].cpu().numpy()
+                kept["labels"] = labels[:T].cpu().numpy()
+                kept["outputs"] = outputs_to_list(out, cu_out)
+            rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if extras else None
+            fd = field_timing(pl, db, stream, 10) if extras else None
+            gr = graph_timing(pl, db, stream, max(2, steps // 2)) if extras else None
+            model.close()
+            cache.close()
+            return wall, per, kern, st, tiles, rx, fd, gr
 
-    def run_path(precision: str, steps: int, warmup: int, prof: bool, extras: bool = False):
-        """Time `steps` whole-path steps; with extras, also the recognizer and
-        schema-field paths on the same resident batch."""
-        model = api.Model(cfg, blob, precision, act_scales=scales if precision == "fp8" else None)
-        cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
-        pl = Pipeline(model, cache)
-        db = DeviceBatch(rb)
-        stream = torch.cuda.current_stream()
-        tiles, _ = pl.autotune(T, B)
-        groups = model.get_tiles()[1]
-        tiles = [f"{model.tile_configs()[t]}_g{g if g else 'auto'}" for t, g in zip(tiles, groups)]
-        for _ in range(warmup):
-            pl.step(db)
-        torch.cuda.synchronize()
-        classes = ["qkv", "attn", "oproj", "ffn1", "ffn2", "ln", "embed", "cls"]
-        if prof:
-            for k in classes:
-                api.prof_enable(k, True)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev[0].record(stream)
-        for i in range(steps):
-            pl.step(db)
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-        kern = {}
-        if prof:
-            for k in classes:
-                kern[k] = api.prof_read(k)
-                api.prof_enable(k, False)
-        st = cache.stats()
-        rx = recognizer_timing(pl, db, stream, max(2, steps // 2)) if extras else None
-        fd = field_timing(pl, db, stream, 10) if extras else None
-        gr = graph_timing(pl, db, stream, max(2, steps // 2)) if extras else None
-        model.close()
-        cache.close()
-        return wall, per, kern, st, tiles, rx, fd, gr
-
-    def graph_timing(pl, db, stream, steps: int) -> dict:
-        """ner_forward over the batch as one HIP graph (ner_forward_capture)
-        against the same call launched kernel by kernel; labels compared."""
-        lab_e, _, mg_e = pl.ner(db, stream=stream)
-        ws = pl._buf("ner_graph", pl.model.workspace_size(db.T, db.B))
-        lab_g = torch.empty_like(lab_e)
-        mg_g = torch.empty_like(mg_e)
-        g = api.ner_forward_capture(pl.model, db.ids, db.cu, db.B, db.T, lab_g, None, mg_g, ws, ws.numel())
-        g.launch(stream)
-        torch.cuda.synchronize()
-        same = bool(torch.equal(lab_e, lab_g) and torch.equal(mg_e, mg_g))
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record(stream)
-        for _ in range(steps):
-            pl.ner(db, stream=stream)
-        ev[1].record(stream)
-        ev[2].record(stream)
-        for _ in range(steps):
+        def graph_timing(pl, db, stream, steps: int) -> dict:
+            """ner_forward over the batch as one HIP graph (ner_forward_capture)
+            against the same call launched kernel by kernel; labels compared."""
+            lab_e, _, mg_e = pl.ner(db, stream=stream)
+            ws = pl._buf("ner_graph", pl.model.workspace_size(db.T, db.B))
+            lab_g = torch.empty_like(lab_e)
+            mg_g = torch.empty_like(mg_e)
+            g = api.ner_forward_capture(pl.model, db.ids, db.cu, db.B, db.T, lab_g, None, mg_g, ws, ws.numel())
             g.launch(stream)
-        ev[3].record(stream)
-        torch.cuda.synchronize()
-        g.close()
-        return {"eager_ner_ms": ev[0].elapsed_time(ev[1]) / steps, "graph_ner_ms": ev[2].elapsed_time(ev[3]) / steps,
-                "labels_and_margins_equal": same}
+            torch.cuda.synchronize()
+            same = bool(torch.equal(lab_e, lab_g) and torch.equal(mg_e, mg_g))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record(stream)
+            for _ in range(steps):
+                pl.ner(db, stream=stream)
+            ev[1].record(stream)
+            ev[2].record(stream)
+            for _ in range(steps):
+                g.launch(stream)
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            g.close()
+            return {"eager_ner_ms": ev[0].elapsed_time(ev[1]) / steps,
+                    "graph_ner_ms": ev[2].elapsed_time(ev[3]) / steps, "labels_and_margins_equal": same}
 
-    def field_timing(pl, db, stream, steps: int) -> dict:
-        """The schema-configured path (whole-field spans of the generator's
-        field names, then substitution; no NER) over the same batch."""
-        from synth.records import _FIELD_OF
-        config = {n: rb.type_names.index(t) + 1 for t, names in _FIELD_OF.items() if t in rb.type_names
-                  for n in names}
-        pl.step_fields(db, config)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
-        ms_f = []
-        for i in range(steps):
-            ev[2 * i].record(stream)
-            spans, cu_f, out, cu_out = pl.step_fields(db, config, stream=stream)
-            ev[2 * i + 1].record(stream)
-        torch.cuda.synchronize()
-        ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        pl.fields(db, config, stream=stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return {"value": db.n_bytes / (ms * 1e-3), "unit": "text bytes/s", "ms_per_step": ms,
-                "field_spans_ms": e0.elapsed_time(e1), "text_bytes": db.n_bytes, "records": db.B,
-                "spans": int(cu_f[-1].item()), "fields": len(config),
-                "paper_context": "with the schema configuration the paper reports 34,341 KB/s (D2, CSV) and "
-                                 "31,272 KB/s (D3) on an RTX 5060 Ti + Ryzen 5 8600G (Table VI)"}
+        def field_timing(pl, db, stream, steps: int) -> dict:
+            """The schema-configured path (whole-field spans of the generator's
+            field names, then substitution; no NER) over the same batch."""
+            from synth.records import _FIELD_OF
+            config = {n: rb.type_names.index(t) + 1 for t, names in _FIELD_OF.items() if t in rb.type_names
+                      for n in names}
+            pl.step_fields(db, config)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+            for i in range(steps):
+                ev[2 * i].record(stream)
+                spans, cu_f, out, cu_out = pl.step_fields(db, config, stream=stream)
+                ev[2 * i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pl.fields(db, config, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return {"value": db.n_bytes / (ms * 1e-3), "unit": "text bytes/s", "ms_per_step": ms,
+                    "field_spans_ms": e0.elapsed_time(e1), "text_bytes": db.n_bytes, "records": db.B,
+                    "spans": int(cu_f[-1].item()), "fields": len(config),
+                    "paper_context": "with the schema configuration the paper reports 34,341 KB/s (D2, CSV) and "
+                                     "31,272 KB/s (D3) on an RTX 5060 Ti + Ryzen 5 8600G (Table VI)"}
 
-    def recognizer_timing(pl, db, stream, steps: int) -> dict:
-        """The same step with the pattern recognizers merged into the NER spans,
-        and recognize_spans alone (HIP events on its stream) over the batch text."""
-        pl.step(db, recognizers=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+        def recognizer_timing(pl, db, stream, steps: int) -> dict:
+            """The same step with the pattern recognizers merged into the NER spans,
+            and recognize_spans alone (HIP events on its stream) over the batch text."""
             pl.step(db, recognizers=True)
-        torch.cuda.synchronize()
-        wall_r = time.perf_counter() - t0
-        labels, _, _ = pl.ner(db, logits=False, margin=False, stream=stream)
-        spans, cu_spans, cap = pl.spans(db, labels, stream=stream)
-        reps = 10
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
-        for i in range(reps):
-            ev[2 * i].record(stream)
-            _, cu_r, _ = pl.recognize(db, spans, cu_spans, cap, stream=stream)
-            ev[2 * i + 1].record(stream)
-        torch.cuda.synchronize()
-        ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
-        return {"value": T * steps / wall_r, "unit": "tokens/s", "ms_per_step": wall_r / steps * 1e3,
-                "recognize_ms": ms, "text_bytes": db.n_bytes, "text_GBps": db.n_bytes / (ms * 1e-3) / 1e9,
-                "ner_spans": int(cu_spans[-1].item()), "merged_spans": int(cu_r[-1].item()),
-                "recognizers": api.RECOGNIZERS}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pl.step(db, recognizers=True)
+            torch.cuda.synchronize()
+            wall_r = time.perf_counter() - t0
+            labels, _, _ = pl.ner(db, logits=False, margin=False, stream=stream)
+            spans, cu_spans, cap = pl.spans(db, labels, stream=stream)
+            reps = 10
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+            for i in range(reps):
+                ev[2 * i].record(stream)
+                _, cu_r, _ = pl.recognize(db, spans, cu_spans, cap, stream=stream)
+                ev[2 * i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+            return {"value": T * steps / wall_r, "unit": "tokens/s", "ms_per_step": wall_r / steps * 1e3,
+                    "recognize_ms": ms, "text_bytes": db.n_bytes, "text_GBps": db.n_bytes / (ms * 1e-3) / 1e9,
+                    "ner_spans": int(cu_spans[-1].item()), "merged_spans": int(cu_r[-1].item()),
+                    "recognizers": api.RECOGNIZERS}
 
-    wall, per, kern, cstats, tiles, rx, fd, gr = run_path(wl.precision, a.steps, a.warmup, prof=True,
-                                                      extras=not a.no_recognizers)
-    tokens_per_s = T * a.steps / wall
-    # dominant kernel class (largest total time) against its roofline
-    gemm_tok = gemm_flops_per_token(cfg)
-    total_att = attention_flops(cu, cfg)
-    dom = max(kern, key=lambda k: kern[k]["ms"])
-    d = kern[dom]
-    if dom in gemm_tok:
-        flops_per_launch = gemm_tok[dom] * T
-        bound, peak, unit = "mfma", PEAK_FLOPS[wl.precision], "TFLOP/s"
-    elif dom == "attn":
-        flops_per_launch = total_att
-        bound, peak, unit = "mfma", PEAK_FLOPS["bf16" if wl.precision != "fp32" else "fp32"], "TFLOP/s"
-    else:
-        flops_per_launch = None
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    achieved = flops_per_launch / (avg_ms * 1e-3) if flops_per_launch else None
-    tile_of = dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles))
-    traffic, traffic_src = counter_traffic(wl.name, dom, tile_of.get(dom))
-    roofline = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
-                "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
-                "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch}
-    breakdown = {}
-    for k, v in kern.items():
-        if v["launches"]:
-            f = gemm_tok[k] * T * v["launches"] if k in gemm_tok else (total_att * v["launches"] if k == "attn" else 0)
-            breakdown[k] = {"launches": v["launches"], "ms_per_step": v["ms"] / a.steps,
-                            "tflops": (f / (v["ms"] * 1e-3) / 1e12) if f else None}
-    flops = path_flops(cfg, cu)
-    out = {
-        "metric": "NER+pseudonymize tokens/sec/GPU",
-        "value": tokens_per_s,
-        "unit": "tokens/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": wall / a.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": wl.precision,
-        "data": "synthetic",
-        "config": {"workload": wl.name, "records": B, "tokens": T, "layers": cfg.n_layers, "hidden": cfg.hidden,
-                   "heads": cfg.n_heads, "ffn": cfg.ffn, "vocab": cfg.vocab, "labels": cfg.n_labels,
-                   "lengths": list(wl.lengths), "packing": "varlen, no padding", "parallelism": "single GPU"},
-        "roofline": roofline,
-        "path_tflops": flops / (wall / a.steps) / 1e12,
-        "path_mfma_frac": flops / (wall / a.steps) / PEAK_FLOPS[wl.precision],
-        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
-                            "mean": float(per.mean())},
-        "kernels": breakdown,
-        "pcache": cstats,
-        "gemm_tiles": dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles)),
-        "input_gen_s": gen_s,
-    }
-    if rx is not None:
-        out["with_recognizers"] = rx
-    if fd is not None:
-        out["schema_fields"] = fd
-    if gr is not None:
-        out["ner_graph"] = gr
-    if not a.no_fp32 and wl.precision != "fp32":
-        w32, per32, _, _, _, _, _, _ = run_path("fp32", max(2, a.steps // 4), 1, prof=False)
-        tps32 = T * max(2, a.steps // 4) / w32
-        out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
-    if not a.no_serve and wl.name == "base_bf16":
+        wall, per, kern, cstats, tiles, rx, fd, gr = run_path(wl.precision, steps, warmup, prof=True, extras=extras)
+        tokens_per_s = T * steps / wall
+        # dominant kernel class (largest total time) against its roofline
+        gemm_tok = gemm_flops_per_token(cfg)
+        total_att = attention_flops(cu, cfg)
+        dom = max(kern, key=lambda k: kern[k]["ms"])
+        d = kern[dom]
+        peak_key = wl.precision
+        if dom in gemm_tok:
+            flops_per_launch = gemm_tok[dom] * T
+        elif dom == "attn":
+            flops_per_launch = total_att
+            peak_key = "bf16" if wl.precision != "fp32" else "fp32"   # attention runs on bf16 operands
+        else:
+            flops_per_launch = None
+        peak = PEAK_FLOPS[peak_key]
+        avg_ms = d["ms"] / max(d["launches"], 1)
+        achieved = flops_per_launch / (avg_ms * 1e-3) if flops_per_launch else None
+        tile_of = dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles))
+        traffic, traffic_src = counter_traffic(wl.name, dom, tile_of.get(dom))
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
+                    "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch, "peak_dtype": peak_key}
+        breakdown = {}
+        for k, v in kern.items():
+            if v["launches"]:
+                f = gemm_tok[k] * T * v["launches"] if k in gemm_tok else (
+                    total_att * v["launches"] if k == "attn" else 0)
+                breakdown[k] = {"launches": v["launches"], "ms_per_step": v["ms"] / steps,
+                                "tflops": (f / (v["ms"] * 1e-3) / 1e12) if f else None}
+        flops = path_flops(cfg, cu)
+        out = {
+            "metric": "NER+pseudonymize tokens/sec/GPU",
+            "value": tokens_per_s,
+            "unit": "tokens/s",
+            "n_gpus": 1,
+            "steps": steps,
+            "warmup": warmup,
+            "ms_per_step": wall / steps * 1e3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": wl.precision,
+            "data": "synthetic",
+            "config": {"workload": wl.name, "records": B, "tokens": T, "layers": cfg.n_layers, "hidden": cfg.hidden,
+                       "heads": cfg.n_heads, "ffn": cfg.ffn, "vocab": cfg.vocab, "labels": cfg.n_labels,
+                       "lengths": list(wl.lengths), "packing": "varlen, no padding", "parallelism": "single GPU"},
+            "roofline": roofline,
+            "path_tflops": flops / (wall / steps) / 1e12,
+            "path_mfma_frac": flops / (wall / steps) / PEAK_FLOPS[wl.precision],
+            "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                                "mean": float(per.mean())},
+            "kernels": breakdown,
+            "pcache": cstats,
+            "gemm_tiles": dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles)),
+            "input_gen_s": gen_s,
+        }
+        if rx is not None:
+            out["with_recognizers"] = rx
+        if fd is not None:
+            out["schema_fields"] = fd
+        if gr is not None:
+            out["ner_graph"] = gr
+        if fp32 and wl.precision != "fp32":
+            w32, per32, _, _, _, _, _, _ = run_path("fp32", max(2, steps // 4), 1, prof=False)
+            tps32 = T * max(2, steps // 4) / w32
+            out["fp32_path"] = {"value": tps32, "unit": "tokens/s", "speedup": tokens_per_s / tps32}
+        ctx = {"wl": wl, "rb": rb, "W": W, "key": key, "scales": scales, "gpu": kept}
+        return out, ctx
+
+    out, ctx = path_bench(a.workload, a.steps, a.warmup, extras=not a.no_recognizers, fp32=not a.no_fp32,
+                          keep_logits=not a.no_cpu)
+    if not a.no_serve and a.workload == "base_bf16":
         # request latency under streaming load (the serving workload at one
         # rate, short); `--serve RATES` runs the full sweep
         sv = serve_bench([100.0], 6.0, 1.5, log=sys.stderr)
@@ -599,8 +676,22 @@ def main() -> int:
                           "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tokens_per_s": r["tokens_per_s"],
                           "offered_tokens_per_s": r["offered_tokens_per_s"], "failed": r["failed"],
                           "seconds": 6.0, "config": sv["config"]}
+    fp8 = None
+    if not a.no_fp8 and a.workload == "base_bf16":
+        # the FP8-E4M3 path on its own workload (24 layers, h1024), a few steps
+        print("[bench] large_fp8 path", file=sys.stderr, flush=True)
+        fp8, fctx = path_bench("large_fp8", a.fp8_steps, 1, extras=False, fp32=False, keep_logits=not a.no_cpu)
+        out["fp8_path"] = {k: fp8[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "roofline",
+                                               "path_tflops", "path_mfma_frac", "kernels", "gemm_tiles")}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, rb, W, key, a.cpu_budget)
+        base, pure = cpu_baseline(ctx["wl"], ctx["rb"], ctx["W"], ctx["key"], a.cpu_budget)
+        out["cpu_baseline"] = base
+        out["parity"] = parity_leg(ctx["wl"], ctx["rb"], ctx["W"], pure, ctx["gpu"], ctx["scales"])
+        if fp8 is not None:
+            # a short sample of the FP8 workload (24-layer oracle: a few records)
+            _, fpure = cpu_baseline(fctx["wl"], fctx["rb"], fctx["W"], fctx["key"], a.cpu_budget / 3)
+            out["fp8_path"]["parity"] = parity_leg(fctx["wl"], fctx["rb"], fctx["W"], fpure, fctx["gpu"],
+                                                   fctx["scales"])
     print(json.dumps(out), flush=True)
     return 0
 

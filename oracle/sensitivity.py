@@ -66,6 +66,21 @@ def perturbed_precision(mode: str, seed: int, act_scales=None, eps: float = EPS)
     return _Perturbed(mode, eps, seed, act_scales)
 
 
+def ambiguous_tokens(labels, zq, tokens, runs) -> list:
+    """The tokens among ``tokens`` where another reduced-precision evaluation
+    may legitimately give ``labels``: for some perturbed run (logits, labels,
+    margins of the oracle perturbed by 1e-7 before each bf16 rounding, on the
+    same tokens) the run gives that label there, or the run's margin there is
+    below the run's own largest logit deviation from the rounding oracle zq."""
+    out = []
+    for t in tokens:
+        for zn, ln, mn in runs:
+            if ln[t] == labels[t] or mn[t] < np.abs(zn - zq).max():
+                out.append(int(t))
+                break
+    return out
+
+
 def perturbed_forward(W, cfg, ids, cu_seqlens, mode: str, seed: int, act_scales=None, eps: float = EPS,
                       window: int = 0, stride: int = 0):
     """Logits, labels and margins of the perturbed reading (one seed)."""

@@ -122,6 +122,7 @@ def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
     of accepted tokens is printed, and may not exceed three times (at least
     two) the number of labels above 1e-2 that the perturbed oracle itself
     flips.  Returns that number."""
+    from oracle import sensitivity
     conf = mq > MARGIN
     bad = np.nonzero(conf & (lab != lq))[0]
     accepted, own_flips = [], 0
@@ -129,11 +130,7 @@ def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
         runs = [perturbed(s) for s in seeds]
         for zn, ln, mn in runs:
             own_flips = max(own_flips, int((conf & (ln != lq)).sum()))
-        for t in bad:
-            for zn, ln, mn in runs:
-                if ln[t] == lab[t] or mn[t] < np.abs(zn - zq).max():
-                    accepted.append(int(t))
-                    break
+        accepted = sensitivity.ambiguous_tokens(lab, zq, bad, runs)
     rejected = sorted(set(bad.tolist()) - set(accepted))
     say(f"  label gate: {int(conf.sum())} tokens above margin 1e-2, {len(bad)} differ, "
         f"{len(accepted)} accepted as ambiguous (perturbed oracle flips {own_flips})")

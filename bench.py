@@ -480,6 +480,10 @@ def main() -> int:
             db = DeviceBatch(rb)
             stream = torch.cuda.current_stream()
             tiles, _ = pl.autotune(T, B)
+            attn_pick, attn_times = pl.autotune_attention(db)
+            kept["attn_config"] = {"chosen": model.attn_configs()[attn_pick] if attn_pick >= 0 else "fp32",
+                                   "times_ms": {n: float(t) for n, t in zip(model.attn_configs(), attn_times)
+                                                if t >= 0}}
             groups = model.get_tiles()[1]
             tiles = [f"{model.tile_configs()[t]}_g{g if g else 'auto'}" for t, g in zip(tiles, groups)]
             for _ in range(warmup):
@@ -650,6 +654,7 @@ def main() -> int:
             "kernels": breakdown,
             "pcache": cstats,
             "gemm_tiles": dict(zip(["qkv", "oproj", "ffn1", "ffn2"], tiles)),
+            "attention_tiles": kept.get("attn_config"),
             "input_gen_s": gen_s,
         }
         if rx is not None:
@@ -682,7 +687,8 @@ def main() -> int:
         print("[bench] large_fp8 path", file=sys.stderr, flush=True)
         fp8, fctx = path_bench("large_fp8", a.fp8_steps, 1, extras=False, fp32=False, keep_logits=not a.no_cpu)
         out["fp8_path"] = {k: fp8[k] for k in ("value", "unit", "ms_per_step", "steps", "config", "roofline",
-                                               "path_tflops", "path_mfma_frac", "kernels", "gemm_tiles")}
+                                               "path_tflops", "path_mfma_frac", "kernels", "gemm_tiles",
+                                               "attention_tiles")}
     if not a.no_cpu:
         base, pure = cpu_baseline(ctx["wl"], ctx["rb"], ctx["W"], ctx["key"], a.cpu_budget)
         out["cpu_baseline"] = base

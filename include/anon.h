@@ -178,6 +178,26 @@ anon_status anon_model_get_tiles(const anon_model* model, int32_t tiles[4], int3
 int32_t anon_tile_config_count(anon_precision precision);
 const char* anon_tile_config_name(anon_precision precision, int32_t config);
 
+/* Attention tile autotuner: times every attention tile configuration of a
+ * BF16/FP8 model (query rows per work item, keys per LDS tile, ring stages)
+ * on the given packed batch's record lengths (random Q, K, V of T rows in
+ * the workspace, which must hold anon_ner_workspace_size(T, B) bytes) and
+ * keeps the fastest for later calls.  Every configuration gives the same
+ * bits (each query row sees the same keys in the same order), so the choice
+ * only changes speed.  chosen: out (may be NULL); times_ms: out, mean time
+ * of each configuration, max_configs entries (may be NULL).  FP32 models
+ * have one attention kernel: ANON_OK, nothing timed.  Synchronises the
+ * stream. */
+anon_status anon_autotune_attention(anon_model* model, const int32_t* d_cu_seqlens, int32_t B, int32_t T,
+                                    void* d_workspace, size_t ws_bytes, void* stream, int32_t* chosen,
+                                    float* times_ms, int32_t max_configs);
+/* Set (-1 = default) or read the attention tile configuration; the number
+ * of configurations and the name of one. */
+anon_status anon_model_set_attn_config(anon_model* model, int32_t config);
+int32_t anon_model_get_attn_config(const anon_model* model);
+int32_t anon_attn_config_count(void);
+const char* anon_attn_config_name(int32_t config);
+
 /* Hidden state after the first n_layers layers (0 = after the embedding
  * LayerNorm) as FP32 [T, hidden] in d_hidden: the activations ner_forward
  * computes, exposed for layer-by-layer checking.  Same workspace rule. */

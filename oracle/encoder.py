@@ -25,7 +25,8 @@ bfloat16 at exactly the points where the GPU's BF16 path stores a value:
 both operands of every GEMM, the stored hidden state after each LayerNorm
 (which is also the residual input of the next sublayer), the residual sum
 x + sublayer(x) that each LayerNorm reads, Q/K/V, the attention
-probabilities (exp(s - row max)) before they multiply V, the attention
+probabilities before they multiply V (taken against the power of two at or
+above the row maximum, see attention()), the attention
 output, and the GELU output.  Dot products, LayerNorm statistics, the softmax
 max/sum and the classifier stay float64 (FP32 on the GPU).  "fp8" additionally rounds the inputs of the
 QKV, output-projection, FFN1 and FFN2 GEMMs to FP8-E4M3 with static
@@ -60,16 +61,27 @@ def softmax_rows(s: np.ndarray) -> np.ndarray:
 def attention(q: np.ndarray, k: np.ndarray, v: np.ndarray, round_p=None) -> np.ndarray:
     """Full bidirectional attention of one record.  q, k, v: [L, H, d] -> [L, H, d].
 
-    With ``round_p`` the unnormalised probabilities exp(s - max) are rounded
-    before they multiply V, and the result is divided by the unrounded row
-    sum (the GPU's order).
+    Without ``round_p``: softmax(q k^T / sqrt(d)) v, with the row maximum
+    subtracted before the exponential.  With ``round_p`` (the reduced-
+    precision reading) the unnormalised probabilities are taken against the
+    power of two at or above the row maximum, p = 2^(s log2(e) - c) with
+    c = ceil(max(s) log2(e)), rounded by ``round_p`` before they multiply v,
+    and the result is divided by the sum of the unrounded p.  Softmax does not
+    depend on the reference; the reference only fixes where p is rounded, and
+    any power of two at or above the maximum gives the same rounded values up
+    to that power of two.
     """
     d = q.shape[-1]
     qh, kh, vh = (np.ascontiguousarray(t.transpose(1, 0, 2)) for t in (q, k, v))   # [H, L, d]
     s = qh @ kh.transpose(0, 2, 1) / math.sqrt(d)                                   # [H, Lq, Lk]
-    p = np.exp(s - s.max(axis=-1, keepdims=True))
+    if round_p is None:
+        p = np.exp(s - s.max(axis=-1, keepdims=True))
+        pv = p
+    else:
+        c = np.ceil(s.max(axis=-1, keepdims=True) / math.log(2.0))
+        p = np.exp2(s / math.log(2.0) - c)
+        pv = round_p(p)
     l = p.sum(axis=-1, keepdims=True)
-    pv = p if round_p is None else round_p(p)
     o = (pv @ vh) / l
     return o.transpose(1, 0, 2)
 

@@ -83,6 +83,11 @@ _SIGS = {
     "ner_forward_windowed": ([vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_decode_workspace_size": ([i32, i32, C.POINTER(sz)], i32),
     "decode_spans": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, sz, vp], i32),
+    "anon_autotune_attention": ([vp, vp, i32, i32, vp, sz, vp, C.POINTER(i32), C.POINTER(C.c_float), i32], i32),
+    "anon_model_set_attn_config": ([vp, i32], i32),
+    "anon_model_get_attn_config": ([vp], i32),
+    "anon_attn_config_count": ([], i32),
+    "anon_attn_config_name": ([i32], C.c_char_p),
     "decode_spans_noalloc": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp], i32),
     "anon_recognize_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
     "anon_field_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
@@ -200,6 +205,26 @@ class Model:
         _check("anon_autotune", lib().anon_autotune(self.handle, T, ptr(d_workspace), ws_bytes,
                                                     stream_handle(stream), chosen, times, n))
         return list(chosen), np.array(times[:], dtype=np.float32).reshape(4, n)
+
+    @staticmethod
+    def attn_configs() -> list[str]:
+        return [lib().anon_attn_config_name(i).decode() for i in range(lib().anon_attn_config_count())]
+
+    def autotune_attention(self, d_cu_seqlens, B: int, T: int, d_workspace, ws_bytes: int, stream=None):
+        """Pick the fastest attention tiles on this batch's lengths; returns (chosen, times_ms[n])."""
+        n = len(self.attn_configs())
+        chosen = i32()
+        times = (C.c_float * n)()
+        _check("anon_autotune_attention",
+               lib().anon_autotune_attention(self.handle, ptr(d_cu_seqlens), B, T, ptr(d_workspace), ws_bytes,
+                                             stream_handle(stream), C.byref(chosen), times, n))
+        return chosen.value, np.array(times[:], dtype=np.float32)
+
+    def set_attn_config(self, config: int):
+        _check("anon_model_set_attn_config", lib().anon_model_set_attn_config(self.handle, int(config)))
+
+    def attn_config(self) -> int:
+        return lib().anon_model_get_attn_config(self.handle)
 
     def set_tiles(self, tiles):
         t = (i32 * 4)(*[int(x) for x in tiles])

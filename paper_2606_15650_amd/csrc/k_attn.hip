@@ -4,21 +4,32 @@
 // the same record only (bidirectional encoder attention).  Q already carries
 // the 1/sqrt(d) = 1/8 factor (applied exactly in the QKV GEMM epilogue).
 //
-// Two kernels.  BF16 operands (records of at most 512 keys): one workgroup
-// per (record, head) holds the record's whole K and V in LDS, V read back
-// transposed (attn_resident_kernel, below).  FP32 operands: work item =
-// (q-block of 32*WAVES rows of one record, head); the block streams the
-// record's keys in tiles of 64, K rows and V^T staged in LDS.  In both, each
-// wave owns 32 query rows and computes S^T = K Q^T with 32x32 MFMAs, so that
-// every lane holds the scores of one query row.  Records longer than one key
-// block take two passes over their keys: the first finds each row's exact
-// maximum, the second forms p = exp(s - max) once (FP32, base-2
-// exponentials), sums it in FP32, rounds it to the operand type and
-// accumulates O^T += V^T P^T in FP32.  Rounding p relative to the final
-// maximum (not a running one) makes the rounded values a function of the
-// record alone, identical to the definition softmax(s) = exp(s - max) / sum.
-// The MFMA k-index of P^T is a permutation of the 32 keys of a block; V^T is
-// read from LDS with the same permutation, so the contraction is exact.
+// BF16 operands (attn_stream_kernel): a persistent grid walks a work list of
+// (record, head, block of 32*W query rows), longest records first.  Each
+// workgroup streams the record's keys in tiles of KT through a two-stage LDS
+// ring (K and V rows copied global -> LDS directly, XOR-swizzled), shared by
+// its W waves, the next tile (also the next item's first) in flight while
+// one is used; each wave owns 32 query rows and forms S^T = K Q^T with
+// 32x32 MFMAs, so every lane holds the scores of one query row.  One pass:
+// the probabilities are p = 2^(s log2(e) - r) against a running reference r
+// that is an integer, the smallest one at or above max(s) log2(e) over the
+// keys seen so far (updated every 64 keys, whatever the tile); when r grows,
+// the FP32 output and row sum are rescaled by the exact power of two
+// 2^(r_old - r_new).  A power-of-two reference scales every p by a power of
+// two, so the bf16-rounded p are those of the final reference: the same
+// values as rounding 2^(s log2(e) - ceil(max(s) log2(e))) with the record's
+// true maximum, whatever the order of the keys.  The row sum is of the
+// unrounded p; O^T += V^T P^T accumulates in FP32 and is divided by it at the
+// end.  The MFMA k-index of P^T is a permutation of the 16 keys of a step; V
+// is read transposed from LDS (ds_read_b64_tr_b16) in the same order.
+//
+// FP32 operands (attn_kernel, the plain FP32 path): work item = (q-block of
+// 32*WAVES rows of one record, head); the block streams the record's keys in
+// tiles of 64, K rows and V^T staged in LDS, in two passes: the first finds
+// each row's exact maximum, the second forms p = exp(s - max) (FP32, base-2
+// exponentials), sums it and accumulates O^T += V^T P^T.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace anon {
@@ -261,212 +272,265 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
   }
 }
 
-// Record-resident variant (bf16 operands, records of at most RMAX keys).
-// One workgroup per (record, head) stages the record's whole K (row-major)
-// and V^T in LDS once; its waves then take 32-row query chunks in turn and
-// run both passes over the resident keys with no further barrier.  The V^T
-// row stride (RMAX + 12 elements, 6 mod 64 dwords) keeps the 8-byte reads of
-// 32 lanes on distinct banks.  Records are binned by length so that RMAX and
-// the wave count follow the record (see kClassMax).
-// LDS bytes of a record-resident workgroup (V rows unpadded, K rows padded
-// by 8 elements) and the waves per SIMD that as many workgroups as fit
-// in the 160 KB of a CU's LDS bring; the register budget is held to that
-// occupancy.
-constexpr int resident_lds_bytes(int rmax) { return (rmax * D + rmax * (D + 8)) * 2; }
-constexpr int resident_waves_per_eu(int rmax, int waves) {
-  return (163840 / resident_lds_bytes(rmax)) * waves / 4;
-}
+// ---- BF16 streaming kernel ------------------------------------------------
+// Tile configurations: W waves (32 query rows each, so 32*W rows per work
+// item), KT keys per LDS tile, WPE waves per SIMD the register budget is
+// held to.  Results do not depend on the configuration: every query row sees
+// the same keys in the same 64-key reference steps.
+struct AttnCfg {
+  int w, kt, wpe;
+  const char* name;
+};
+#define ANON_ATTN_CFGS(X)                    \
+  X(0, 4, 64, 4, "attn_w4_kt64_o4")          \
+  X(1, 4, 64, 3, "attn_w4_kt64_o3")          \
+  X(2, 8, 64, 4, "attn_w8_kt64_o4")          \
+  X(3, 2, 64, 3, "attn_w2_kt64_o3")          \
+  X(4, 8, 128, 3, "attn_w8_kt128_o3")
+#define ANON_ATTN_ROW(i, w, kt, wpe, name) {w, kt, wpe, name},
+const AttnCfg kAttnCfg[] = {ANON_ATTN_CFGS(ANON_ATTN_ROW)};
+constexpr int kAttnCfgs = (int)(sizeof(kAttnCfg) / sizeof(AttnCfg));
+constexpr int kAttnDefault = 0;
+constexpr int kRowBytes = D * 2;  // one K or V row (64 bf16)
+constexpr int kStages = 2;        // LDS ring: the tile being used and the one in flight
 
-template <typename TO, int RMAX, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, resident_waves_per_eu(RMAX, WAVES)) void attn_resident_kernel(const bf16_t* __restrict__ qkv,
-                                                                   TO* __restrict__ out,
-                                                                   const int4* __restrict__ recs,
-                                                                   const int* __restrict__ n_recs, int hidden,
-                                                                   float out_inv_scale) {
+// K rows: 16-byte chunk c of row r sits in slot c ^ ((r >> 1) & 7), so the
+// 16-byte fragment reads of 16 consecutive rows (one logical chunk) fall on
+// 16 distinct bank groups.  V rows: chunk c of row r sits in slot
+// c ^ (4 * ((r >> 1) & 1)), the layout the transposing reads expect
+// (vtr_lane_offset).
+__device__ __forceinline__ int kswz(int r) { return (r >> 1) & 7; }
+__device__ __forceinline__ int vswz(int r) { return ((r >> 1) & 1) << 2; }
+
+// A workgroup's walk over its work items and their key tiles.
+struct Walk {
+  int wi, t, nt;       // work item, tile within it, tiles of the item
+  int base, L, q0, head;
+};
+
+template <typename TO, int W, int KT, int WPE>
+__global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* __restrict__ qkv,
+                                                                  TO* __restrict__ out,
+                                                                  const int4* __restrict__ items,
+                                                                  const int* __restrict__ n_items, int n_heads,
+                                                                  int hidden, float out_inv_scale) {
   typedef AMfma<bf16_t> MF;
   typedef bf16x8 frag;
-  constexpr int KS = D + 8;       // K row stride (16 bytes of padding)
   constexpr float LOG2E = 1.4426950408889634f;
-  const int rb = blockIdx.x;
-  if (rb >= *n_recs) return;
-  const int head = blockIdx.y;
-  const int4 desc = recs[rb];
-  const int base = desc.x, L = desc.y;
+  constexpr int TILE = KT * kRowBytes;   // bytes of the K (or V) rows of one tile
+  constexpr int STAGE = 2 * TILE;
+  constexpr int INS = KT / 8;            // load instructions per tile and matrix (8 rows of 128 B each)
+  static_assert(INS % W == 0, "every wave issues the same number of loads");
+  constexpr int IPW = INS / W;           // per wave, per matrix
+  constexpr int NB = KT / 32;            // 32-key blocks per tile
+  static_assert(KT % 64 == 0, "tile shape");
+  __shared__ __align__(1024) char smem[kStages * STAGE];
+
+  const int n_work = *n_items * n_heads;
+  const int tid = threadIdx.x, lane = tid & 63, hh = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ld = 3 * hidden;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, hh = lane >> 5;
-
-  // V first: its reads then sit below 64 KB, within reach of the
-  // instructions' immediate offsets.  V is kept row-major (key, d), 64
-  // elements per row, with bit 5 of the column flipped in rows whose bit 1 is
-  // set; the PV step reads it transposed (vfrag_tr).
-  __shared__ __align__(16) bf16_t lds[RMAX * D + RMAX * KS];
-  static_assert(sizeof(lds) == resident_lds_bytes(RMAX), "LDS size");
-  bf16_t* const Vs = lds;
-  bf16_t* const Ks = lds + RMAX * D;
-
-  // A workgroup has one wave per 32 keys of the class bound, so every thread
-  // stages exactly NSTG 16-byte chunks of K and of V, and every wave owns at
-  // most one 32-row query chunk.  All of the thread's loads (its K and V
-  // chunks and its wave's Q fragments) are issued before the first LDS
-  // write, so the workgroup waits for one memory round trip, not one per
-  // chunk.
-  constexpr int NT = WAVES * 64;
-  constexpr int NSTG = RMAX * 8 / NT;
-  static_assert(RMAX == 32 * WAVES && NSTG * NT == RMAX * 8, "one wave per 32 keys");
-  const int Lp = (L + 31) & ~31;  // keys padded with zeros to whole 32-key blocks
-  intx4 kv[NSTG], vv[NSTG];
+  // this lane's part of each load instruction: row (lane / 8) of the 8,
+  // LDS slot (lane % 8); and its K fragment offsets within a stage
+  const int lrow = lane >> 3, lslot = lane & 7;
+  int koff[NB][D / 16];
 #pragma unroll
-  for (int i = 0; i < NSTG; ++i) {
-    const int c = tid + i * NT, r = c >> 3, cc = c & 7;
-    kv[i] = intx4{0, 0, 0, 0};
-    vv[i] = intx4{0, 0, 0, 0};
-    if (r < L) {
-      const bf16_t* src = qkv + (size_t)(base + r) * ld + head * D + cc * 8;
-      kv[i] = *(const intx4*)(src + hidden);
-      vv[i] = *(const intx4*)(src + 2 * hidden);
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int kk = 0; kk < D / 16; ++kk) {
+      const int row = b * 32 + (lane & 31);
+      koff[b][kk] = row * kRowBytes + (((kk * 2 + hh) ^ kswz(row)) * 16);
     }
+  const int vl_off0 = TILE + 2 * vtr_lane_offset(lane, 0), vl_off1 = TILE + 2 * vtr_lane_offset(lane, 1);
+
+  auto start = [&](Walk& c, int wi) {
+    c.wi = wi;
+    c.t = 0;
+    if (wi < n_work) {
+      const int it = wi / n_heads;
+      c.head = wi - it * n_heads;
+      const int4 d = items[it];  // (first token, length, first query row, -)
+      c.base = d.x, c.L = d.y, c.q0 = d.z;
+      c.nt = (c.L + KT - 1) / KT;
+    }
+  };
+  // tile c.t of work item c into ring stage st: rows past the record re-read
+  // its last row (never used: their scores are masked, their p are zero)
+  // the lane's byte offsets within a K row and a V row (its swizzled chunk)
+  int kchunk[IPW], vchunk[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    const int row = (wave * IPW + i) * 8 + lrow;
+    kchunk[i] = (lslot ^ kswz(row)) * 16;
+    vchunk[i] = 2 * hidden + (lslot ^ vswz(row)) * 16;
   }
-  const int nkb = Lp / 32;
-  const int nqc = (L + 31) / 32;
-  const bool partial = (L & 31) != 0;  // only the last key block has missing keys
-  const int qc = wave;
-  const int qrow = qc * 32 + (lane & 31);
+  auto issue = [&](const Walk& c, int st) {
+    // the record's first K row of this head (uniform), then 32-bit offsets
+    const char* kb = (const char*)(qkv + (size_t)c.base * ld + hidden + c.head * D);
+    char* sk = smem + st * STAGE;
+    const int last = c.L - 1;
+#pragma unroll
+    for (int i = 0; i < IPW; ++i) {
+      const int row = (wave * IPW + i) * 8 + lrow;
+      const uint32_t ro = (uint32_t)min(c.t * KT + row, last) * (uint32_t)(2 * ld);
+      dma16(kb + ro + kchunk[i], sk + (wave * IPW + i) * 1024);
+      dma16(kb + ro + vchunk[i], sk + TILE + (wave * IPW + i) * 1024);
+    }
+  };
   frag qf[D / 16];
+  auto load_q = [&](const Walk& c) {
+    const int qrow = c.q0 + wave * 32 + (lane & 31);
 #pragma unroll
-  for (int kk = 0; kk < D / 16; ++kk)
-    qf[kk] = qrow < L ? *(const frag*)(qkv + (size_t)(base + qrow) * ld + head * D + kk * 16 + hh * 8) : frag{};
-#pragma unroll
-  for (int i = 0; i < NSTG; ++i) {
-    const int c = tid + i * NT, r = c >> 3, cc = c & 7;
-    if (r < Lp) {
-      *(intx4*)&Ks[r * KS + cc * 8] = kv[i];
-      *(intx4*)&Vs[r * D + (cc ^ (((r >> 1) & 1) << 2)) * 8] = vv[i];
-    }
-  }
-  __syncthreads();
+    for (int kk = 0; kk < D / 16; ++kk)
+      qf[kk] = qrow < c.L ? *(const frag*)(qkv + (size_t)(c.base + qrow) * ld + c.head * D + kk * 16 + hh * 8)
+                          : frag{};
+  };
 
-  if (qc < nqc) {
-    // raw scores S^T of key block kb; missing keys of the last block -> -inf
-    auto qk = [&](int kb, floatx16& s) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) s[r] = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < D / 16; ++kk) {
-        const frag a = *(const frag*)&Ks[(kb * 32 + (lane & 31)) * KS + kk * 16 + hh * 8];
-        s = MF::mma(a, qf[kk], s);
-      }
-      if (partial && kb == nkb - 1) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3) >= L) s[r] = -INFINITY;
-      }
-    };
-    const bf16_t* const vl0 = Vs + vtr_lane_offset(lane, 0);
-    const bf16_t* const vl1 = Vs + vtr_lane_offset(lane, 1);
-    // pass 1: row maximum of the raw scores (the scale is positive, so the
-    // maximum of the scaled scores is the scaled maximum)
-    // Both passes are software-pipelined two blocks deep: the next block's
-    // QK^T MFMAs are issued before the current block's VALU work (maximum,
-    // exponentials), which then runs while the matrix core is busy.
-    float mraw = -INFINITY;
-    auto rowmax = [&](const floatx16& s) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) mraw = fmaxf(mraw, s[r]);
-    };
-    floatx16 sa, sb;
-    qk(0, sa);
-    if (nkb > 1) {
-      for (int kb = 0; kb < nkb; kb += 2) {
-        if (kb + 1 < nkb) qk(kb + 1, sb);
-        rowmax(sa);
-        if (kb + 1 < nkb) {
-          if (kb + 2 < nkb) qk(kb + 2, sa);
-          rowmax(sb);
-        }
-      }
-    } else {
-      rowmax(sa);
-    }
-    // sa and sb now hold the raw scores of the last two blocks, nkb-2 and
-    // nkb-1 (sa holds nkb-1 when nkb is odd), or sa holds block 0 alone
-    mraw = fmaxf(mraw, __shfl_xor(mraw, 32, 64));
-    // K fragments are read from LDS again in pass 2 rather than kept live
-    // across pass 1 (no instruction: it only stops the compiler from reusing
-    // pass-1 loads, which would cost registers it does not have)
-    __asm__ volatile("" ::: "memory");
-    floatx16 o[2];
+  // The issue walk runs one tile ahead of the compute walk, also across work
+  // items: while the last tile of an item is used, the first tile of the
+  // next is in flight, and the next item's Q rows are loaded right after.
+  Walk cw, iw;
+  start(cw, blockIdx.x);
+  if (cw.wi >= n_work) return;
+  iw = cw;
+  issue(iw, 0);
+  load_q(cw);
+  floatx16 o[2];
+  float lsum, ref;
+  auto reset = [&]() {
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[0][r] = o[1][r] = 0.f;
-    float lsum = 0.f;
-    // pass 2: p = 2^(s*log2(e) - max*log2(e)) = exp(s - max), O^T += V^T P^T
-    auto pv = [&](int kb, floatx16& s, floatx16 (&acc)[2]) {
-      const float mb = mraw * LOG2E;
+    lsum = 0.f;
+    ref = -INFINITY;
+  };
+  reset();
+
+  // one tile from stage ST (a compile-time constant: the loop body is
+  // unrolled over the two stages); returns false when the walk is over
+  auto step = [&](auto stc) -> bool {
+    constexpr int ST = decltype(stc)::value;
+    // tile cw.t (and, after a switch, the item's Q rows) has landed for this
+    // wave; after the barrier for everyone, who have also finished the
+    // previous tile, whose stage takes the next one
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (++iw.t == iw.nt) start(iw, iw.wi + gridDim.x);
+    if (iw.wi < n_work) issue(iw, ST ^ 1);
+    const bool active = cw.q0 + wave * 32 < cw.L;
+    if (active) {
+      const char* ks = smem + ST * STAGE;
+      const bool last_partial = cw.t == cw.nt - 1 && (cw.L % KT) != 0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float p = exp2_fast(fmaf(s[r], LOG2E, -mb));
-        s[r] = p;
-        lsum += p;
-      }
+      for (int h64 = 0; h64 < KT / 64; ++h64) {
+        // keys of this 64-key step still inside the record (uniform)
+        const int nv = cw.L - (cw.t * KT + h64 * 64);
+        if (nv <= 0) break;
+        // scores of the 64 keys [t*KT + 64*h64, +64): two 32-key blocks
+        // (the second only if it holds keys of the record)
+        const bool two = nv > 32;
+        floatx16 s[2];
 #pragma unroll
-      for (int stp = 0; stp < 2; ++stp) {
-        const frag pb = pfrag<bf16_t>(s, stp);
+        for (int b = 0; b < 2; ++b) {
+          if (b == 1 && !two) break;
 #pragma unroll
-        for (int db = 0; db < 2; ++db) acc[db] = MF::mma(vfrag_tr(db ? vl1 : vl0, kb, stp), pb, acc[db]);
-      }
-    };
-    // Pass 2 takes the blocks in the order nkb-2, nkb-1 (still in registers,
-    // not recomputed), then 0 .. nkb-3: a fixed order given by the record's
-    // length alone.  X holds the first block of the order, Y the second.
-    auto pass2 = [&](floatx16& X, floatx16& Y) {
-      const int first = nkb > 1 ? nkb - 2 : 0;
-      auto seq = [&](int i) { return i < 2 ? first + i : i - 2; };
-      pv(seq(0), X, o);
-      for (int i = 1; i < nkb; i += 2) {
-        if (i + 1 < nkb) qk(seq(i + 1), X);
-        pv(seq(i), Y, o);
-        if (i + 1 < nkb) {
-          if (i + 2 < nkb) qk(seq(i + 2), Y);
-          pv(seq(i + 1), X, o);
+          for (int r = 0; r < 16; ++r) s[b][r] = 0.f;
+#pragma unroll
+          for (int kk = 0; kk < D / 16; ++kk) {
+            const frag a = *(const frag*)(ks + koff[h64 * 2 + b][kk]);
+            s[b] = MF::mma(a, qf[kk], s[b]);
+          }
+        }
+        // the block holding the record's end: keys past it -> -inf
+        if (last_partial && nv < 64 && (nv & 31) != 0) {
+          const int b = nv >> 5;
+          const int thr = (nv & 31) - hh * 4;  // key (r>>2)*8 + (r&3) of this lane is valid iff below thr
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const bool past = (r >> 2) * 8 + (r & 3) >= thr;
+            if (b == 0) s[0][r] = past ? -INFINITY : s[0][r];
+            else s[1][r] = past ? -INFINITY : s[1][r];
+          }
+        }
+        // reference update: the smallest integer at or above max * log2(e)
+        float mx = -INFINITY;
+        if (two) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) mx = fmaxf(mx, fmaxf(s[0][r], s[1][r]));
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[0][r]);
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+        const float rn = ceilf(mx * LOG2E);
+        if (rn > ref) {  // never for 64 keys all past the record (mx = -inf)
+          if (ref > -INFINITY) {
+            const int dl = (int)(ref - rn);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              o[0][r] = ldexpf(o[0][r], dl);
+              o[1][r] = ldexpf(o[1][r], dl);
+            }
+            lsum = ldexpf(lsum, dl);
+          }
+          ref = rn;
+        }
+        // p = 2^(s log2(e) - ref); row sums of the unrounded p; O^T += V^T P^T
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (b == 1 && !two) break;  // a block wholly past the record adds nothing
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float p = exp2_fast(fmaf(s[b][r], LOG2E, -ref));
+            s[b][r] = p;
+            lsum += p;
+          }
+#pragma unroll
+          for (int stp = 0; stp < 2; ++stp) {
+            const frag pb = pfrag<bf16_t>(s[b], stp);
+            const int kb = h64 * 2 + b;
+            const bf16_t* v0 = (const bf16_t*)(smem + ST * STAGE + vl_off0);
+            const bf16_t* v1 = (const bf16_t*)(smem + ST * STAGE + vl_off1);
+            o[0] = MF::mma(vfrag_tr(v0, kb, stp), pb, o[0]);
+            o[1] = MF::mma(vfrag_tr(v1, kb, stp), pb, o[1]);
+          }
         }
       }
-    };
-    if (nkb > 1 && (nkb & 1)) {
+    }
+    if (++cw.t < cw.nt) return true;
+    // the item is done: normalise and store, then start the next one
+    if (active) {
+      const int qrow = cw.q0 + wave * 32 + (lane & 31);
+      const float inv = 1.0f / (lsum + __shfl_xor(lsum, 32, 64));
+      if (qrow < cw.L) {
+        TO* dst = out + (size_t)(cw.base + qrow) * hidden + cw.head * D;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float t = sa[r];
-        sa[r] = sb[r];
-        sb[r] = t;
+        for (int db = 0; db < 2; ++db)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            float v = o[db][r] * inv;
+            // FP8 output: round to bf16 (the stored attention output), then
+            // scale and round to E4M3
+            if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * out_inv_scale;
+            st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), v);
+          }
       }
     }
-    pass2(sa, sb);
-    const float ltot = lsum + __shfl_xor(lsum, 32, 64);
-    const float inv = 1.0f / ltot;
-    if (qrow < L) {
-      TO* dst = out + (size_t)(base + qrow) * hidden + head * D;
-#pragma unroll
-      for (int db = 0; db < 2; ++db)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          float v = o[db][r] * inv;
-          if (sizeof(TO) == 1) v = static_cast<float>(static_cast<bf16_t>(v)) * out_inv_scale;
-          st(dst + db * 32 + (r >> 2) * 8 + hh * 4 + (r & 3), v);
-        }
-    }
+    start(cw, cw.wi + gridDim.x);
+    if (cw.wi >= n_work) return false;
+    load_q(cw);
+    reset();
+    return true;
+  };
+  while (step(std::integral_constant<int, 0>()) && step(std::integral_constant<int, 1>())) {
   }
 }
 
 constexpr int kWaves = 4;
 constexpr int kBQ = 32 * kWaves;
-// Record-resident length classes: records of (kClassMax[c-1], kClassMax[c]]
-// keys go to a kernel whose LDS holds kClassMax[c] keys and whose waves
-// cover that many query rows (32 each), so shorter records fit more
-// workgroups per CU and leave fewer waves idle.
-constexpr int kClasses = 4;
-constexpr int kClassMax[kClasses] = {128, 256, 384, 512};
-constexpr int kResidentMax = 512;
 
-// One workgroup: validates cu_seqlens and lists (record, q-block) items for
-// the records whose length lies in [lo, hi].
+// One workgroup: validates cu_seqlens and lists (first token, length, first
+// query row, record) items of bq query rows for the records whose length
+// lies in [lo, hi].
 __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
                                                         int lo, int hi, int bq, int4* __restrict__ qblocks,
                                                         int max_q, int* __restrict__ n_qblocks, uint32_t* err) {
@@ -512,71 +576,143 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
   }
 }
 
-bool resident(ElemType t, int max_len) { return t == ET_BF16 && max_len <= kResidentMax; }
-
-template <typename TO>
-void launch_resident(const bf16_t* q, TO* out, const int4* items, int per_class, const int* counts, int n_heads,
-                     int hidden, float out_inv_scale, hipStream_t s) {
-  const dim3 grid(per_class, n_heads);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 128, 4>), grid, dim3(4 * 64), 0, s, q, out, items, counts,
-                     hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 256, 8>), grid, dim3(8 * 64), 0, s, q, out,
-                     items + per_class, counts + 1, hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 384, 12>), grid, dim3(12 * 64), 0, s, q, out,
-                     items + 2 * per_class, counts + 2, hidden, out_inv_scale);
-  hipLaunchKernelGGL((attn_resident_kernel<TO, 512, 16>), grid, dim3(16 * 64), 0, s, q, out,
-                     items + 3 * per_class, counts + 3, hidden, out_inv_scale);
-}
-
-}  // namespace
-
-int attn_plan_items(ElemType t, int max_len, int T, int B) {
-  // resident: one item per record in each length class;
-  // tiled: one item per 128-row q-block
-  return resident(t, max_len) ? kClasses * (B + 1) : T / kBQ + B + 1;
-}
-
-int attn_plan_counts() { return kClasses; }
-
-void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
-                      int* counts, uint32_t* err, hipStream_t s) {
-  if (resident(t, max_len)) {
-    const int per = max_items / kClasses;
-    for (int c = 0; c < kClasses; ++c) {
-      const int lo = c == 0 ? 1 : kClassMax[c - 1] + 1;
-      hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, lo, kClassMax[c],
-                         1 << 30, items + c * per, per, counts + c, err);
+// One workgroup: the BF16 kernel's work list, longest records first (in
+// bins of 32 keys), each record split into items of bq query rows.
+__global__ __launch_bounds__(1024) void stream_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
+                                                           int bq, int4* __restrict__ items, int max_items,
+                                                           int* __restrict__ n_items, uint32_t* err) {
+  __shared__ int sums[1024];
+  __shared__ int run;
+  const int tid = threadIdx.x;
+  const int per = (B + 1023) / 1024;
+  const int s0 = min(B, tid * per), s1 = min(B, s0 + per);
+  bool bad = false;
+  for (int s = s0; s < s1; ++s) {
+    const int a = cu[s], b = cu[s + 1];
+    if (a < 0 || b > T || b < a || b - a > max_len) bad = true;
+  }
+  if (tid == 0 && (cu[0] != 0 || cu[B] != T)) bad = true;
+  if (bad) raise_error(err, ANON_ERR_SEQLENS);
+  if (tid == 0) run = 0;
+  const int nbins = (max_len + 31) / 32;
+  for (int bin = nbins - 1; bin >= 0; --bin) {
+    int cnt = 0;
+    for (int s = s0; s < s1; ++s) {
+      const int a = cu[s], b = cu[s + 1], L = b - a;
+      if (a < 0 || b > T || L < 1 || L > max_len || (L - 1) / 32 != bin) continue;
+      cnt += (L + bq - 1) / bq;
     }
-  } else {
-    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 0, max_len, kBQ,
-                       items, max_items, counts, err);
+    __syncthreads();  // `run` is final, `sums` free
+    sums[tid] = cnt;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int v = tid >= o ? sums[tid - o] : 0;
+      __syncthreads();
+      sums[tid] += v;
+      __syncthreads();
+    }
+    int pos = run + sums[tid] - cnt;
+    for (int s = s0; s < s1; ++s) {
+      const int a = cu[s], b = cu[s + 1], L = b - a;
+      if (a < 0 || b > T || L < 1 || L > max_len || (L - 1) / 32 != bin) continue;
+      for (int q = 0; q < L; q += bq, ++pos)
+        if (pos < max_items) items[pos] = int4{a, L, q, s};
+    }
+    __syncthreads();  // every thread has read `run`
+    if (tid == 1023) run += sums[1023];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (run > max_items) raise_error(err, ANON_ERR_SEQLENS);
+    *n_items = min(run, max_items);
   }
 }
 
-void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* counts,
-                      int max_len, int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale,
+bool streamed(ElemType t) { return t == ET_BF16; }
+
+int workgroups_per_cu(const AttnCfg& c) {
+  const int by_regs = c.wpe * 4 / c.w;
+  const int by_lds = 163840 / (kStages * 2 * c.kt * kRowBytes);
+  return std::max(1, std::min(by_regs, by_lds));
+}
+
+template <typename TO, int W, int KT, int WPE>
+void launch_stream(const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads, int hidden,
+                   float out_inv_scale, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((attn_stream_kernel<TO, W, KT, WPE>), dim3(grid), dim3(W * 64), 0, s, qkv, out, items,
+                     n_items, n_heads, hidden, out_inv_scale);
+}
+
+template <typename TO>
+void dispatch_stream(int ci, const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads,
+                     int hidden, float out_inv_scale, int grid, hipStream_t s) {
+#define ANON_ATTN_CASE(i, w, kt, wpe, name)                                                            \
+  case i:                                                                                              \
+    launch_stream<TO, w, kt, wpe>(qkv, out, items, n_items, n_heads, hidden, out_inv_scale, grid, s); \
+    return;
+  switch (ci) { ANON_ATTN_CFGS(ANON_ATTN_CASE) }
+#undef ANON_ATTN_CASE
+}
+
+int cfg_index(int config) { return config >= 0 && config < kAttnCfgs ? config : kAttnDefault; }
+
+}  // namespace
+
+int attn_num_configs() { return kAttnCfgs; }
+
+const char* attn_config_name(int config) {
+  return config >= 0 && config < kAttnCfgs ? kAttnCfg[config].name : "?";
+}
+
+int attn_plan_items(ElemType t, int config, int T, int B) {
+  // at most T / bq + B items of bq query rows
+  const int bq = streamed(t) ? 32 * kAttnCfg[cfg_index(config)].w : kBQ;
+  return T / bq + B + 1;
+}
+
+void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int config, int4* items,
+                      int max_items, int* n_items, uint32_t* err, hipStream_t s) {
+  if (streamed(t)) {
+    const int bq = 32 * kAttnCfg[cfg_index(config)].w;
+    hipLaunchKernelGGL(stream_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, bq, items,
+                       max_items, n_items, err);
+  } else {
+    hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 0, max_len, kBQ,
+                       items, max_items, n_items, err);
+  }
+}
+
+void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* n_items,
+                      int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale, int config,
                       hipStream_t s) {
   if (max_items <= 0) return;
-  if (resident(t, max_len)) {
-    const int per = max_items / kClasses;
+  if (streamed(t)) {
+    const int ci = cfg_index(config);
+    // a persistent grid: as many workgroups as the CUs hold at once (no more
+    // than there can be work items)
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = (int)std::min<int64_t>((int64_t)n_cu * workgroups_per_cu(kAttnCfg[ci]),
+                                            (int64_t)max_items * n_heads);
     if (out_t == ET_FP8)
-      launch_resident(static_cast<const bf16_t*>(qkv), (fp8_t*)out, items, per, counts, n_heads, hidden,
-                      out_inv_scale, s);
+      dispatch_stream(ci, static_cast<const bf16_t*>(qkv), (fp8_t*)out, items, n_items, n_heads, hidden,
+                      out_inv_scale, grid, s);
     else
-      launch_resident(static_cast<const bf16_t*>(qkv), (bf16_t*)out, items, per, counts, n_heads, hidden,
-                      out_inv_scale, s);
+      dispatch_stream(ci, static_cast<const bf16_t*>(qkv), (bf16_t*)out, items, n_items, n_heads, hidden,
+                      out_inv_scale, grid, s);
     return;
   }
   dim3 grid(max_items, n_heads);
   if (t == ET_F32) {
     hipLaunchKernelGGL((attn_kernel<float, float, kWaves>), grid, dim3(kWaves * 64), 0, s, (const float*)qkv,
-                       (float*)out, items, counts, hidden, out_inv_scale);
+                       (float*)out, items, n_items, hidden, out_inv_scale);
   } else if (out_t == ET_FP8) {
     hipLaunchKernelGGL((attn_kernel<bf16_t, fp8_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (fp8_t*)out, items, counts, hidden, out_inv_scale);
+                       (fp8_t*)out, items, n_items, hidden, out_inv_scale);
   } else {
     hipLaunchKernelGGL((attn_kernel<bf16_t, bf16_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (bf16_t*)out, items, counts, hidden, out_inv_scale);
+                       (bf16_t*)out, items, n_items, hidden, out_inv_scale);
   }
 }
 

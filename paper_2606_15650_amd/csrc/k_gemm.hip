@@ -380,18 +380,6 @@ __device__ __forceinline__ int lds_swz(int r) {
   return CPR == 8 ? (r >> 1) & 7 : (r >> 2) & 3;
 }
 
-__device__ __forceinline__ void dma16(const void* g, char* l) {
-  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
-                                   (__attribute__((address_space(3))) void*)l, 16, 0, 0);
-}
-
-// s_waitcnt vmcnt(n) alone (expcnt and lgkmcnt left at their maxima)
-template <int n>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(n >= 0 && n < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
-
 // Instruction order of one k-step (a scheduling region): the next k-step's
 // fragment reads go out two per MFMA from the first MFMA on, so their
 // latency hides behind the rest of the step's MFMA chain; then the ring

@@ -33,15 +33,17 @@ const char* gemm_config_name(ElemType in, int config);
 bool gemm_config_fits(ElemType in, int config, int N, int K);
 
 // ---- attention ------------------------------------------------------------
-// Attention work list: validates cu_seqlens and lists the work items of the
-// kernel variant that serves (operand type, max record length).  `counts`
-// holds attn_plan_counts() ints.
-int attn_plan_items(ElemType t, int max_len, int T, int B);
-int attn_plan_counts();  // ints the plan writes to `counts`
-void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int4* items, int max_items,
-                      int* counts, uint32_t* err, hipStream_t s);
-void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* counts,
-                      int max_len, int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale,
+// Work list of the attention kernel (validates cu_seqlens on the device).
+// `config` picks the BF16 kernel's tile configuration (attn_num_configs();
+// -1: default); the FP32 kernel has one.  `items` holds attn_plan_items()
+// entries; `n_items` (one int, device) receives their count.
+int attn_num_configs();
+const char* attn_config_name(int config);
+int attn_plan_items(ElemType t, int config, int T, int B);
+void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int config, int4* items,
+                      int max_items, int* n_items, uint32_t* err, hipStream_t s);
+void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* n_items,
+                      int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale, int config,
                       hipStream_t s);
 
 // ---- row-wise kernels -----------------------------------------------------

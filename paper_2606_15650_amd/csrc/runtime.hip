@@ -124,6 +124,7 @@ struct anon_model {
   ElemType qkv_t;   // Q, K, V and attention operands
   int gemm_cfg[4] = {-1, -1, -1, -1};
   int gemm_gm[4] = {0, 0, 0, 0};  // row blocks per tile group (0: by shape)
+  int attn_cfg = -1;               // attention tile configuration (-1: default)
 };
 
 const anon_model_config* anon::model_config(const anon_model* m) { return &m->cfg; }
@@ -352,9 +353,11 @@ static void enc_layout(const anon_model* m, int T, int B, Carver& k, EncWs& w) {
   w.attn = k.take<uint8_t>(T * h * g);
   w.y = k.take<uint8_t>(T * h * a);
   w.ffn = k.take<uint8_t>(T * f * g);
-  w.max_q = attn_plan_items(m->qkv_t, m->cfg.max_pos, T, B);
+  // room for the work list of any attention configuration
+  w.max_q = 0;
+  for (int c = 0; c < attn_num_configs(); ++c) w.max_q = std::max(w.max_q, attn_plan_items(m->qkv_t, c, T, B));
   w.qblocks = k.take<int4>(w.max_q);
-  w.nq = k.take<int>(attn_plan_counts());
+  w.nq = k.take<int>(1);
 }
 
 static anon_status check_batch(const anon_model* m, const void* d_ids, const void* d_cu, int B, int T) {
@@ -376,7 +379,7 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
   const int h = c.hidden, f = c.ffn;
   uint32_t* err = error_word_ptr();
   const bool fp8 = m->gemm_t == ET_FP8;
-  launch_attn_plan(cu, B, T, c.max_pos, m->qkv_t, w.qblocks, w.max_q, w.nq, err, s);
+  launch_attn_plan(cu, B, T, c.max_pos, m->qkv_t, m->attn_cfg, w.qblocks, w.max_q, w.nq, err, s);
   {
     ProfScope ps(KC_EMBED, s, 0.0);
     launch_embed_ln(ids, cu, B, T, m->tok_emb, m->pos_emb, m->emb_g, m->emb_b, c.ln_eps, c.vocab, c.max_pos, h, w.x,
@@ -411,8 +414,8 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     }
     {
       ProfScope ps(KC_ATTN, s, 0.0);
-      launch_attention(w.qkv, w.attn, w.qblocks, w.max_q, w.nq, c.max_pos, c.n_heads, h, m->qkv_t, m->gemm_t,
-                       fp8 ? 1.f / L.sa[1] : 1.f, s);
+      launch_attention(w.qkv, w.attn, w.qblocks, w.max_q, w.nq, c.n_heads, h, m->qkv_t, m->gemm_t,
+                       fp8 ? 1.f / L.sa[1] : 1.f, m->attn_cfg, s);
     }
     // output projection + bias + residual -> FP32, then LayerNorm 1
     g.A = w.attn;
@@ -719,6 +722,80 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
   ANON_HIP_CHECK(hipGetLastError());
   return st;
 }
+
+anon_status anon_autotune_attention(anon_model* m, const int32_t* d_cu_seqlens, int32_t B, int32_t T,
+                                    void* d_workspace, size_t ws_bytes, void* stream, int32_t* chosen,
+                                    float* times_ms, int32_t max_configs) {
+  clear_error();
+  if (!m || B < 1 || T < 1 || !d_cu_seqlens) return set_error(ANON_EINVAL, "bad arguments");
+  if ((int64_t)T > (int64_t)B * m->cfg.max_pos) return set_error(ANON_EINVAL, "T exceeds B * max_pos");
+  if (!d_workspace || ws_bytes < enc_ws_bytes(m, T, B)) return set_error(ANON_ECAPACITY, "workspace too small");
+  const int ncfg = attn_num_configs();
+  if (times_ms)
+    for (int c = 0; c < max_configs; ++c) times_ms[c] = -1.f;
+  if (m->qkv_t != ET_BF16) {
+    if (chosen) *chosen = -1;
+    return ANON_OK;
+  }
+  ANON_HIP_CHECK(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)stream;
+  Carver k(d_workspace, ws_bytes);
+  EncWs w;
+  enc_layout(m, T, B, k, w);
+  const anon_model_config& c = m->cfg;
+  launch_fill_random(w.qkv, ET_BF16, (int64_t)T * 3 * c.hidden, 0x9e37u, s);
+  uint32_t* err = error_word_ptr();
+  const bool fp8 = m->gemm_t == ET_FP8;
+  hipEvent_t e0, e1;
+  ANON_HIP_CHECK(hipEventCreate(&e0));
+  ANON_HIP_CHECK(hipEventCreate(&e1));
+  std::vector<float> best(ncfg, 1e30f);
+  anon_status st = ANON_OK;
+  for (int round = 0; round < 2 && st == ANON_OK; ++round) {
+    for (int ci = 0; ci < ncfg; ++ci) {
+      launch_attn_plan(d_cu_seqlens, B, T, c.max_pos, ET_BF16, ci, w.qblocks, w.max_q, w.nq, err, s);
+      launch_attention(w.qkv, w.attn, w.qblocks, w.max_q, w.nq, c.n_heads, c.hidden, ET_BF16, m->gemm_t,
+                       fp8 ? 1.f / m->layers[0].sa[1] : 1.f, ci, s);
+      const int reps = 3;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r)
+        launch_attention(w.qkv, w.attn, w.qblocks, w.max_q, w.nq, c.n_heads, c.hidden, ET_BF16, m->gemm_t,
+                         fp8 ? 1.f / m->layers[0].sa[1] : 1.f, ci, s);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = set_error(ANON_EDEVICE, "autotune: attention kernel failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best[ci] = std::min(best[ci], ms / reps);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ANON_OK) return st;
+  // near-ties go to the default configuration
+  int pick = 0;
+  for (int ci = 1; ci < ncfg; ++ci)
+    if (best[ci] < best[pick] * (pick == 0 ? 0.99f : 1.0f)) pick = ci;
+  m->attn_cfg = pick;
+  if (chosen) *chosen = pick;
+  if (times_ms)
+    for (int ci = 0; ci < std::min(ncfg, (int)max_configs); ++ci) times_ms[ci] = best[ci];
+  ANON_HIP_CHECK(hipGetLastError());
+  return ANON_OK;
+}
+
+anon_status anon_model_set_attn_config(anon_model* m, int32_t config) {
+  if (!m) return set_error(ANON_EINVAL, "model is NULL");
+  if (config < -1 || config >= attn_num_configs()) return set_error(ANON_EINVAL, "no such attention configuration");
+  m->attn_cfg = config;
+  return ANON_OK;
+}
+
+int32_t anon_model_get_attn_config(const anon_model* m) { return m ? m->attn_cfg : -1; }
+int32_t anon_attn_config_count(void) { return attn_num_configs(); }
+const char* anon_attn_config_name(int32_t config) { return attn_config_name(config); }
 
 anon_status anon_encoder_hidden(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
                                 int32_t T, int32_t n_layers, float* d_hidden, void* d_workspace, size_t ws_bytes,

@@ -76,6 +76,11 @@ class Pipeline:
         ws = self._buf("ner", self.model.workspace_size(T, max(B, 1)))
         return self.model.autotune(T, ws, ws.numel(), stream)
 
+    def autotune_attention(self, db: DeviceBatch, stream=None):
+        """Let the library time the attention tiles on this batch's lengths and keep the fastest."""
+        ws = self._buf("ner", self.model.workspace_size(db.T, db.B))
+        return self.model.autotune_attention(db.cu, db.B, db.T, ws, ws.numel(), stream)
+
     def hidden(self, db: DeviceBatch, n_layers: int, stream=None) -> torch.Tensor:
         out = torch.empty((max(db.T, 1), self.model.cfg.hidden), dtype=torch.float32, device=self.device)
         ws = self._buf("ner", self.model.workspace_size(db.T, db.B))

@@ -115,12 +115,12 @@ def test_edge_lengths_one_token_and_max_pos(torch_dev):
 
 
 def test_bf16_attention_length_classes_and_block_counts(torch_dev):
-    """BF16 attention keeps each record's K and V^T in LDS, in one of four
-    kernels by length (at most 128, 256, 384, 512 keys), and walks 32-key
-    blocks two at a time.  Lengths at and around every class bound, with
-    partial and whole last blocks and 1 to 16 blocks of both parities, agree
-    with the bf16-rounding oracle, and each record alone gives the bits it
-    gives inside the packed batch."""
+    """BF16 attention streams each record's keys in 64-key tiles (128 in one
+    configuration) with a reference that grows every 64 keys, in work items
+    of 32*W query rows.  Lengths at and around every tile and item bound, with
+    partial and whole last tiles of 1 to 16 32-key blocks, agree with the
+    bf16-rounding oracle, and each record alone gives the bits it gives inside
+    the packed batch."""
     cfg = ModelConfig(n_layers=2, hidden=128, n_heads=2, ffn=256, vocab=500, n_labels=9, max_pos=512)
     W, m = make_model(cfg, "bf16", 4)
     lens = [1, 31, 32, 33, 64, 96, 127, 128, 129, 160, 255, 256, 257, 320, 383, 384, 385, 448, 511, 512]
@@ -139,6 +139,44 @@ def test_bf16_attention_length_classes_and_block_counts(torch_dev):
         a, b = rb.cu_seqlens[r], rb.cu_seqlens[r + 1]
         np.testing.assert_array_equal(z1, z[a:b], err_msg=f"record of {lens[r]} tokens")
         np.testing.assert_array_equal(l1, lab[a:b])
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_attention_configurations_are_bit_identical(torch_dev, precision):
+    """Every attention tile configuration (query rows per item, keys per LDS
+    tile, ring stages) gives the same bits on records that span every tile
+    and item bound, so the attention autotuner never changes a result; the
+    autotuner's pick is one of them."""
+    from paper_2606_15650_amd import api
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+    cfg = ModelConfig(n_layers=2, hidden=256, n_heads=4, ffn=512, vocab=700, n_labels=9, max_pos=512)
+    W = synth.make_weights(cfg, 9)
+    scales = None
+    if precision == "fp8":
+        from oracle import calibrate_fp8
+        sc, _ = calibrate_fp8.calibrate(cfg, W, ("uniform", 16, 512), n_records=8)
+        scales = np.asarray(sc, np.float32).reshape(-1)
+    m = api.Model(cfg, synth.weights_blob(cfg, W), precision, act_scales=scales)
+    lens = [1, 63, 64, 65, 127, 128, 129, 191, 255, 256, 257, 300, 383, 384, 385, 449, 511, 512]
+    rb = synth.generate_records(len(lens), np.array(lens), 4, cfg.vocab, 19)
+    names = m.attn_configs()
+    say(f"[attn configs] {precision}: {names}")
+    ref = None
+    for ci in range(len(names)):
+        m.set_attn_config(ci)
+        lab, z, mg = _run_ner(m, rb)
+        if ref is None:
+            ref = (lab, z)
+        else:
+            np.testing.assert_array_equal(z, ref[1], err_msg=names[ci])
+            np.testing.assert_array_equal(lab, ref[0], err_msg=names[ci])
+    pl = Pipeline(m)
+    chosen, times = pl.autotune_attention(DeviceBatch(rb))
+    say(f"  autotune picked {names[chosen]}; times {np.round(times, 4).tolist()}")
+    assert 0 <= chosen < len(names) and m.attn_config() == chosen
+    lab, z, mg = _run_ner(m, rb)
+    np.testing.assert_array_equal(z, ref[1])
+    m.close()
 
 
 def test_empty_batch_is_a_no_op(tiny_fp32):

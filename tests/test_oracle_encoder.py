@@ -189,3 +189,27 @@ def test_bf16_reading_is_close_to_pure_and_idempotent_storage():
 
 def test_positions_restart_per_record():
     np.testing.assert_array_equal(encoder.positions(np.array([0, 3, 3, 5])), [0, 1, 2, 0, 1])
+
+
+def test_rounded_probabilities_reference_is_a_power_of_two():
+    """The reduced-precision reading rounds p = 2^(s log2 e - c) with c the
+    smallest integer at or above max(s) log2 e.  Pins: (1) with no rounding it
+    is softmax itself (the reference cancels); (2) any larger integer
+    reference rounds to the same values times the power of two (so a
+    single pass whose reference grows reaches the same rounded p); (3) a
+    non-integer reference would not (the rounding point really moves);
+    (4) the largest rounded p lies in [1/2, 1]."""
+    rng = np.random.default_rng(5)
+    L, H, d = 37, 3, 16
+    q, k, v = (rng.normal(size=(L, H, d)) for _ in range(3))
+    ident = encoder.attention(q, k, v, round_p=lambda p: p)
+    np.testing.assert_allclose(ident, encoder.attention(q, k, v), rtol=1e-12, atol=1e-14)
+    s = rng.normal(scale=3.0, size=(200, 64))
+    x = s / np.log(2.0)
+    c = np.ceil(x.max(axis=-1, keepdims=True))
+    p0 = round_bf16(np.exp2(x - c))
+    assert (p0.max(axis=-1) >= 0.5).all() and (p0.max(axis=-1) <= 1.0).all()
+    for shift in (1, 7, 40):
+        np.testing.assert_array_equal(round_bf16(np.exp2(x - (c + shift))) * 2.0 ** shift, p0)
+    moved = round_bf16(np.exp2(x - (c + 0.37))) * 2.0 ** 0.37
+    assert (np.abs(moved - p0) > 0).mean() > 0.3

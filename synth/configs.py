@@ -30,9 +30,47 @@ class ModelConfig:
         return (self.n_labels - 1) // 2
 
 
+@dataclass(frozen=True)
+class ModernConfig:
+    """A ModernBERT-style encoder: pre-LayerNorm layers without biases,
+    rotary position embeddings, global attention every ``global_every``
+    layers (from layer 0) and a sliding window elsewhere (a token sees keys at
+    most ``local_window // 2`` positions away), a gated GELU MLP
+    (``intermediate`` wide), a final LayerNorm and a dense + GELU + LayerNorm
+    head before the token classifier."""
+    n_layers: int
+    hidden: int
+    n_heads: int
+    intermediate: int
+    vocab: int
+    n_labels: int
+    max_pos: int = 8192
+    ln_eps: float = 1e-5
+    local_window: int = 128
+    global_every: int = 3
+    theta_global: float = 160000.0
+    theta_local: float = 10000.0
+
+    @property
+    def head_dim(self) -> int:
+        return self.hidden // self.n_heads
+
+    @property
+    def n_types(self) -> int:
+        return (self.n_labels - 1) // 2
+
+    def is_global(self, layer: int) -> bool:
+        return layer % self.global_every == 0
+
+
 TINY = ModelConfig(n_layers=2, hidden=128, n_heads=2, ffn=512, vocab=8192, n_labels=9)
 BASE = ModelConfig(n_layers=12, hidden=768, n_heads=12, ffn=3072, vocab=30522, n_labels=17)
 LARGE = ModelConfig(n_layers=24, hidden=1024, n_heads=16, ffn=4096, vocab=30522, n_labels=17)
+# ModernBERT-base shapes (22 layers, h768, 12 heads, GeGLU 1152, vocab 50368)
+# and a small one for the parity cases
+MODERN_BASE = ModernConfig(n_layers=22, hidden=768, n_heads=12, intermediate=1152, vocab=50368, n_labels=17)
+MODERN_TINY = ModernConfig(n_layers=4, hidden=128, n_heads=2, intermediate=192, vocab=5000, n_labels=9,
+                           max_pos=1024)
 
 
 @dataclass(frozen=True)
@@ -79,6 +117,10 @@ WORKLOADS = {
     "large_fp8": Workload(
         "large_fp8", LARGE, 16384, ("lognormal", 5.5, 0.7, 16, 512), "fp8",
         notes="24-layer h1024 encoder with FP8-E4M3 GEMMs"),
+    "modern_bf16": Workload(
+        "modern_bf16", MODERN_BASE, 4096, ("lognormal", 5.2, 0.6, 16, 512), "bf16",
+        notes="ModernBERT-style encoder (22 layers, h768, RoPE, local/global attention, GeGLU) on the base "
+              "workload's 4096 records"),
 }
 
 

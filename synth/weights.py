@@ -24,12 +24,29 @@ import math
 import numpy as np
 from scipy import integrate, optimize, stats
 
-from .configs import ModelConfig
+from .configs import ModelConfig, ModernConfig
 
 STD = 0.02
 
 
-def tensor_specs(cfg: ModelConfig) -> list[tuple[str, tuple[int, ...]]]:
+def modern_tensor_specs(cfg: ModernConfig) -> list[tuple[str, tuple[int, ...]]]:
+    """ModernBERT-style encoder (no biases but the classifier's; LayerNorms
+    without shifts; layer 0 has no attention LayerNorm).  wi holds the MLP's
+    input half in columns [0, I) and its gate half in [I, 2I)."""
+    h, I, C = cfg.hidden, cfg.intermediate, cfg.n_labels
+    specs = [("tok_emb", (cfg.vocab, h)), ("emb_ln_g", (h,))]
+    for l in range(cfg.n_layers):
+        if l > 0:
+            specs.append((f"l{l}.attn_ln_g", (h,)))
+        specs += [(f"l{l}.wqkv", (h, 3 * h)), (f"l{l}.wo", (h, h)), (f"l{l}.mlp_ln_g", (h,)),
+                  (f"l{l}.wi", (h, 2 * I)), (f"l{l}.wo2", (I, h))]
+    specs += [("final_ln_g", (h,)), ("head_w", (h, h)), ("head_ln_g", (h,)), ("wc", (h, C)), ("bc", (C,))]
+    return specs
+
+
+def tensor_specs(cfg) -> list[tuple[str, tuple[int, ...]]]:
+    if isinstance(cfg, ModernConfig):
+        return modern_tensor_specs(cfg)
     h, f, C = cfg.hidden, cfg.ffn, cfg.n_labels
     specs = [("tok_emb", (cfg.vocab, h)), ("pos_emb", (cfg.max_pos, h)),
              ("emb_ln_g", (h,)), ("emb_ln_b", (h,))]
@@ -44,7 +61,7 @@ def tensor_specs(cfg: ModelConfig) -> list[tuple[str, tuple[int, ...]]]:
     return specs
 
 
-def o_bias_for(cfg: ModelConfig, o_target: float) -> float:
+def o_bias_for(cfg, o_target: float) -> float:
     """Bias on the O logit giving P(argmax = O) = o_target for i.i.d. N(0, s^2) logits."""
     s = math.sqrt(cfg.hidden) * STD
     k = cfg.n_labels - 1
@@ -56,7 +73,7 @@ def o_bias_for(cfg: ModelConfig, o_target: float) -> float:
     return float(optimize.brentq(lambda d: p_win(d) - o_target, -10 * s, 20 * s))
 
 
-def make_weights(cfg: ModelConfig, seed: int = 0, o_target: float | None = None) -> dict[str, np.ndarray]:
+def make_weights(cfg, seed: int = 0, o_target: float | None = None) -> dict[str, np.ndarray]:
     rng = np.random.default_rng(seed)
     out: dict[str, np.ndarray] = {}
     for name, shape in tensor_specs(cfg):
@@ -70,7 +87,7 @@ def make_weights(cfg: ModelConfig, seed: int = 0, o_target: float | None = None)
     return out
 
 
-def weights_blob(cfg: ModelConfig, weights: dict[str, np.ndarray]) -> np.ndarray:
+def weights_blob(cfg, weights: dict[str, np.ndarray]) -> np.ndarray:
     """The weights as one contiguous FP32 array in :func:`tensor_specs` order."""
     parts = []
     for name, shape in tensor_specs(cfg):

@@ -178,6 +178,54 @@ anon_status anon_model_get_tiles(const anon_model* model, int32_t tiles[4], int3
 int32_t anon_tile_config_count(anon_precision precision);
 const char* anon_tile_config_name(anon_precision precision, int32_t config);
 
+/* ------------------------------------------------------------------------
+ * ModernBERT-style encoder (the paper's SecureModernBERT-NER model of Sec. II
+ * stage 2, used for its accuracy run, Sec. IV-B): pre-LayerNorm layers with
+ * no biases (LayerNorms without shift), rotary position embeddings (base
+ * theta_global on layers 0, global_every, 2*global_every, ..., theta_local
+ * elsewhere), full attention on those global layers and a sliding window on
+ * the others (a token sees the keys at most local_window/2 positions away),
+ * a gated MLP (x += (GELU(u) * g) Wo2 with [u | g] = LN(x) Wi), a final
+ * LayerNorm, a dense + GELU + LayerNorm head and the token classifier.  The
+ * residual stream is kept in FP32; FP32 or BF16 GEMM operands.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_layers, hidden, n_heads, intermediate, vocab, n_labels, max_pos;
+  float ln_eps;
+  int32_t local_window; /* total window width; a token sees local_window/2 keys on each side */
+  int32_t global_every;
+  float theta_global, theta_local;
+} anon_modern_config;
+typedef struct anon_modern anon_modern;
+
+/* h_weights: host FP32 tensors back to back, matrices in x @ W orientation
+ * ([in][out]):  tok_emb [vocab][h], emb_ln_g [h]; per layer l:
+ * (l > 0) attn_ln_g [h], wqkv [h][3h] (columns Q | K | V, head j owns
+ * columns 64j .. 64j+63 of each), wo [h][h], mlp_ln_g [h], wi [h][2I]
+ * (columns: the input half u, then the gate half g), wo2 [I][h]; then
+ * final_ln_g [h], head_w [h][h], head_ln_g [h], wc [h][C], bc [C].  Copied
+ * before return.  Head dimension 64; h = 64 * {1,2,4,8,12,16}; I a multiple
+ * of 32; at most 32 labels.  precision: ANON_FP32 or ANON_BF16. */
+anon_status anon_modern_create(const anon_modern_config* cfg, const float* h_weights, size_t n_floats,
+                               anon_precision precision, int32_t device, anon_modern** out);
+void anon_modern_free(anon_modern* model);
+anon_status anon_modern_workspace_size(const anon_modern* model, int32_t T, int32_t B, size_t* bytes);
+/* As ner_forward, for the ModernBERT-style encoder (positions restart in
+ * every record; a record may be up to max_pos tokens long). */
+anon_status modern_ner_forward(anon_modern* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                               int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                               size_t ws_bytes, void* stream);
+/* The FP32 residual stream after the first n_layers layers (0 = after the
+ * embedding LayerNorm), [T, hidden], for layer-by-layer checking. */
+anon_status anon_modern_hidden(anon_modern* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                               int32_t T, int32_t n_layers, float* d_hidden, void* d_workspace, size_t ws_bytes,
+                               void* stream);
+/* Tile configurations of the five GEMMs (QKV, output projection, gated MLP
+ * input, MLP output, head; -1 = default, names as anon_tile_config_name) and
+ * of the attention (-1 = default, names as anon_attn_config_name). */
+anon_status anon_modern_set_tiles(anon_modern* model, const int32_t tiles[5], int32_t attn_config);
+anon_status anon_modern_get_tiles(const anon_modern* model, int32_t tiles[5], int32_t* attn_config);
+
 /* Attention tile autotuner: times every attention tile configuration of a
  * BF16/FP8 model (query rows per work item, keys per LDS tile, ring stages)
  * on the given packed batch's record lengths (random Q, K, V of T rows in

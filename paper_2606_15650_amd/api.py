@@ -35,6 +35,13 @@ class ModelConfigC(C.Structure):
                 ("vocab", C.c_int32), ("n_labels", C.c_int32), ("max_pos", C.c_int32), ("ln_eps", C.c_float)]
 
 
+class ModernConfigC(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("hidden", C.c_int32), ("n_heads", C.c_int32),
+                ("intermediate", C.c_int32), ("vocab", C.c_int32), ("n_labels", C.c_int32),
+                ("max_pos", C.c_int32), ("ln_eps", C.c_float), ("local_window", C.c_int32),
+                ("global_every", C.c_int32), ("theta_global", C.c_float), ("theta_local", C.c_float)]
+
+
 class SpanC(C.Structure):
     _fields_ = [("record", C.c_int32), ("type", C.c_int32), ("begin", C.c_int64), ("end", C.c_int64)]
 
@@ -88,6 +95,13 @@ _SIGS = {
     "anon_model_get_attn_config": ([vp], i32),
     "anon_attn_config_count": ([], i32),
     "anon_attn_config_name": ([i32], C.c_char_p),
+    "anon_modern_create": ([vp, vp, sz, i32, i32, C.POINTER(vp)], i32),
+    "anon_modern_free": ([vp], None),
+    "anon_modern_workspace_size": ([vp, i32, i32, C.POINTER(sz)], i32),
+    "modern_ner_forward": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], i32),
+    "anon_modern_hidden": ([vp, vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
+    "anon_modern_set_tiles": ([vp, C.POINTER(i32), i32], i32),
+    "anon_modern_get_tiles": ([vp, C.POINTER(i32), C.POINTER(i32)], i32),
     "decode_spans_noalloc": ([vp, vp, vp, i32, i32, i32, vp, i32, vp, vp], i32),
     "anon_recognize_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
     "anon_field_workspace_size": ([i64, i32, C.POINTER(sz)], i32),
@@ -252,11 +266,69 @@ class Model:
             pass
 
 
-def ner_forward(model: Model, d_ids, d_cu_seqlens, B: int, T: int, d_labels, d_logits=None, d_margin=None,
+def ner_forward(model, d_ids, d_cu_seqlens, B: int, T: int, d_labels, d_logits=None, d_margin=None,
                 d_workspace=None, ws_bytes: int = 0, stream=None):
+    if isinstance(model, ModernModel):
+        _check("modern_ner_forward", lib().modern_ner_forward(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T,
+                                                              ptr(d_labels), ptr(d_logits), ptr(d_margin),
+                                                              ptr(d_workspace), ws_bytes, stream_handle(stream)))
+        return
     _check("ner_forward", lib().ner_forward(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T, ptr(d_labels),
                                             ptr(d_logits), ptr(d_margin), ptr(d_workspace), ws_bytes,
                                             stream_handle(stream)))
+
+
+class ModernModel:
+    """A ModernBERT-style encoder uploaded to one device (``anon_modern_create``)."""
+
+    def __init__(self, cfg, weights_blob: np.ndarray, precision: str = "bf16", device: int = 0):
+        blob = np.ascontiguousarray(weights_blob, dtype=np.float32)
+        self.cfg = cfg
+        self.precision = precision
+        c = ModernConfigC(cfg.n_layers, cfg.hidden, cfg.n_heads, cfg.intermediate, cfg.vocab, cfg.n_labels,
+                          cfg.max_pos, cfg.ln_eps, cfg.local_window, cfg.global_every, cfg.theta_global,
+                          cfg.theta_local)
+        h = vp()
+        _check("anon_modern_create", lib().anon_modern_create(C.byref(c), blob.ctypes.data, blob.size,
+                                                              PRECISION[precision], device, C.byref(h)))
+        self.handle = h.value
+
+    def workspace_size(self, T: int, B: int) -> int:
+        n = sz()
+        _check("anon_modern_workspace_size", lib().anon_modern_workspace_size(self.handle, T, B, C.byref(n)))
+        return n.value
+
+    def hidden(self, d_ids, d_cu_seqlens, B: int, T: int, n_layers: int, d_hidden, d_workspace, ws_bytes: int,
+               stream=None):
+        _check("anon_modern_hidden", lib().anon_modern_hidden(self.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T,
+                                                              n_layers, ptr(d_hidden), ptr(d_workspace), ws_bytes,
+                                                              stream_handle(stream)))
+
+    def set_tiles(self, tiles, attn_config: int = -1):
+        t = (i32 * 5)(*[int(x) for x in tiles])
+        _check("anon_modern_set_tiles", lib().anon_modern_set_tiles(self.handle, t, int(attn_config)))
+
+    def get_tiles(self) -> tuple[list[int], int]:
+        t, a = (i32 * 5)(), i32()
+        _check("anon_modern_get_tiles", lib().anon_modern_get_tiles(self.handle, t, C.byref(a)))
+        return list(t), a.value
+
+    def tile_configs(self) -> list[str]:
+        p = PRECISION[self.precision]
+        return [lib().anon_tile_config_name(p, i).decode() for i in range(lib().anon_tile_config_count(p))]
+
+    attn_configs = staticmethod(Model.attn_configs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().anon_modern_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class ForwardGraph:

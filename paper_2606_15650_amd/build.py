@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libanon.so")
 SOURCES = ["runtime.hip", "k_gemm.hip", "k_attn.hip", "k_rows.hip", "k_spans.hip", "k_recog.hip", "k_fields.hip",
-           "k_pseudo.hip", "server.hip"]
+           "k_pseudo.hip", "server.hip", "modern.hip"]
 HEADERS = ["common.hpp", "kernels.hpp"]
 ARCH = "gfx950"
 

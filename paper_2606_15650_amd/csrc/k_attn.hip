@@ -125,7 +125,7 @@ template <typename T, typename TO, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ qkv, TO* __restrict__ out,
                                                           const int4* __restrict__ qblocks,
                                                           const int* __restrict__ n_qblocks, int hidden,
-                                                          float out_inv_scale) {
+                                                          float out_inv_scale, int window) {
   typedef AMfma<T> MF;
   typedef typename MF::frag frag;
   constexpr int NT = WAVES * 64;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 
   constexpr int CPR = D / EPC;  // 16-byte chunks per K/V row
   // scores of the current 64-key tile, base-2 scaled, -inf for missing keys
-  auto scores = [&](floatx16 (&s)[2], int nk) {
+  auto scores = [&](floatx16 (&s)[2], int t0k, int nk) {
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
@@ -181,7 +181,9 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int key = kb * 32 + (r >> 2) * 8 + hh * 4 + (r & 3);
-        const float v = key < nk ? s[kb][r] * LOG2E : -INFINITY;
+        const int dk = qrow - (t0k + key);
+        const bool seen = key < nk && (window <= 0 || (dk <= window && dk >= -window));
+        const float v = seen ? s[kb][r] * LOG2E : -INFINITY;
         s[kb][r] = v;
         mloc = fmaxf(mloc, v);
       }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
       __syncthreads();
       if (active) {
         floatx16 s[2];
-        m = fmaxf(m, scores(s, nk));
+        m = fmaxf(m, scores(s, t0, nk));
       }
     }
   }
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
     __syncthreads();
     if (active) {
       floatx16 s[2];
-      const float mt = scores(s, nk);
+      const float mt = scores(s, t0, nk);
       if (ntiles == 1) m = mt;
       float ps = 0.f;
 #pragma unroll
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
                                                                   TO* __restrict__ out,
                                                                   const int4* __restrict__ items,
                                                                   const int* __restrict__ n_items, int n_heads,
-                                                                  int hidden, float out_inv_scale) {
+                                                                  int hidden, float out_inv_scale, int window) {
   typedef AMfma<bf16_t> MF;
   typedef bf16x8 frag;
   constexpr float LOG2E = 1.4426950408889634f;
@@ -343,15 +345,21 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     }
   const int vl_off0 = TILE + 2 * vtr_lane_offset(lane, 0), vl_off1 = TILE + 2 * vtr_lane_offset(lane, 1);
 
+  // with a window, an item's rows [q0, q0 + 32W) only see the key tiles
+  // that meet [q0 - window, q0 + 32W - 1 + window]
   auto start = [&](Walk& c, int wi) {
     c.wi = wi;
-    c.t = 0;
     if (wi < n_work) {
       const int it = wi / n_heads;
       c.head = wi - it * n_heads;
       const int4 d = items[it];  // (first token, length, first query row, -)
       c.base = d.x, c.L = d.y, c.q0 = d.z;
+      c.t = 0;
       c.nt = (c.L + KT - 1) / KT;
+      if (window > 0) {
+        c.t = max(c.q0 - window, 0) / KT;
+        c.nt = min(c.q0 + 32 * W - 1 + window, c.L - 1) / KT + 1;
+      }
     }
   };
   // tile c.t of work item c into ring stage st: rows past the record re-read
@@ -416,15 +424,24 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     __builtin_amdgcn_s_barrier();
     if (++iw.t == iw.nt) start(iw, iw.wi + gridDim.x);
     if (iw.wi < n_work) issue(iw, ST ^ 1);
-    const bool active = cw.q0 + wave * 32 < cw.L;
+    const int qw = cw.q0 + wave * 32;  // this wave's first query row
+    const bool active = qw < cw.L;
     if (active) {
       const char* ks = smem + ST * STAGE;
-      const bool last_partial = cw.t == cw.nt - 1 && (cw.L % KT) != 0;
+      const bool last_partial = (cw.t + 1) * KT > cw.L;
 #pragma unroll
       for (int h64 = 0; h64 < KT / 64; ++h64) {
         // keys of this 64-key step still inside the record (uniform)
-        const int nv = cw.L - (cw.t * KT + h64 * 64);
+        const int k0 = cw.t * KT + h64 * 64;
+        const int nv = cw.L - k0;
         if (nv <= 0) break;
+        // with a window: steps outside this wave's band are skipped, steps
+        // across its edge are masked key by key
+        bool band_edge = false;
+        if (window > 0) {
+          if (k0 > qw + 31 + window || k0 + 63 < qw - window) continue;
+          band_edge = k0 < qw + 31 - window || k0 + 63 > qw + window;
+        }
         // scores of the 64 keys [t*KT + 64*h64, +64): two 32-key blocks
         // (the second only if it holds keys of the record)
         const bool two = nv > 32;
@@ -438,6 +455,19 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
           for (int kk = 0; kk < D / 16; ++kk) {
             const frag a = *(const frag*)(ks + koff[h64 * 2 + b][kk]);
             s[b] = MF::mma(a, qf[kk], s[b]);
+          }
+        }
+        if (band_edge) {
+          // key k of this lane's query q is seen iff |q - k| <= window
+          const int dq = qw + (lane & 31) - (k0 + hh * 4);  // q - (key of r = 0 in block 0)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            if (b == 1 && !two) break;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int dk = dq - (b * 32 + (r >> 2) * 8 + (r & 3));
+              if (dk > window || dk < -window) s[b][r] = -INFINITY;
+            }
           }
         }
         // the block holding the record's end: keys past it -> -inf
@@ -475,12 +505,15 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
           ref = rn;
         }
         // p = 2^(s log2(e) - ref); row sums of the unrounded p; O^T += V^T P^T
+        // (a row that has seen no key yet has only -inf scores here: any
+        // finite reference gives p = 0)
+        const float nref = ref > -INFINITY ? ref : 0.f;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           if (b == 1 && !two) break;  // a block wholly past the record adds nothing
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const float p = exp2_fast(fmaf(s[b][r], LOG2E, -ref));
+            const float p = exp2_fast(fmaf(s[b][r], LOG2E, -nref));
             s[b][r] = p;
             lsum += p;
           }
@@ -638,17 +671,17 @@ int workgroups_per_cu(const AttnCfg& c) {
 
 template <typename TO, int W, int KT, int WPE>
 void launch_stream(const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads, int hidden,
-                   float out_inv_scale, int grid, hipStream_t s) {
+                   float out_inv_scale, int window, int grid, hipStream_t s) {
   hipLaunchKernelGGL((attn_stream_kernel<TO, W, KT, WPE>), dim3(grid), dim3(W * 64), 0, s, qkv, out, items,
-                     n_items, n_heads, hidden, out_inv_scale);
+                     n_items, n_heads, hidden, out_inv_scale, window);
 }
 
 template <typename TO>
 void dispatch_stream(int ci, const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads,
-                     int hidden, float out_inv_scale, int grid, hipStream_t s) {
-#define ANON_ATTN_CASE(i, w, kt, wpe, name)                                                            \
-  case i:                                                                                              \
-    launch_stream<TO, w, kt, wpe>(qkv, out, items, n_items, n_heads, hidden, out_inv_scale, grid, s); \
+                     int hidden, float out_inv_scale, int window, int grid, hipStream_t s) {
+#define ANON_ATTN_CASE(i, w, kt, wpe, name)                                                                    \
+  case i:                                                                                                      \
+    launch_stream<TO, w, kt, wpe>(qkv, out, items, n_items, n_heads, hidden, out_inv_scale, window, grid, s); \
     return;
   switch (ci) { ANON_ATTN_CFGS(ANON_ATTN_CASE) }
 #undef ANON_ATTN_CASE
@@ -684,7 +717,7 @@ void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType
 
 void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* n_items,
                       int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale, int config,
-                      hipStream_t s) {
+                      hipStream_t s, int window) {
   if (max_items <= 0) return;
   if (streamed(t)) {
     const int ci = cfg_index(config);
@@ -697,22 +730,22 @@ void launch_attention(const void* qkv, void* out, const int4* items, int max_ite
                                             (int64_t)max_items * n_heads);
     if (out_t == ET_FP8)
       dispatch_stream(ci, static_cast<const bf16_t*>(qkv), (fp8_t*)out, items, n_items, n_heads, hidden,
-                      out_inv_scale, grid, s);
+                      out_inv_scale, window, grid, s);
     else
       dispatch_stream(ci, static_cast<const bf16_t*>(qkv), (bf16_t*)out, items, n_items, n_heads, hidden,
-                      out_inv_scale, grid, s);
+                      out_inv_scale, window, grid, s);
     return;
   }
   dim3 grid(max_items, n_heads);
   if (t == ET_F32) {
     hipLaunchKernelGGL((attn_kernel<float, float, kWaves>), grid, dim3(kWaves * 64), 0, s, (const float*)qkv,
-                       (float*)out, items, n_items, hidden, out_inv_scale);
+                       (float*)out, items, n_items, hidden, out_inv_scale, window);
   } else if (out_t == ET_FP8) {
     hipLaunchKernelGGL((attn_kernel<bf16_t, fp8_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (fp8_t*)out, items, n_items, hidden, out_inv_scale);
+                       (fp8_t*)out, items, n_items, hidden, out_inv_scale, window);
   } else {
     hipLaunchKernelGGL((attn_kernel<bf16_t, bf16_t, kWaves>), grid, dim3(kWaves * 64), 0, s, (const bf16_t*)qkv,
-                       (bf16_t*)out, items, n_items, hidden, out_inv_scale);
+                       (bf16_t*)out, items, n_items, hidden, out_inv_scale, window);
   }
 }
 

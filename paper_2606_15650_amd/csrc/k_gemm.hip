@@ -117,6 +117,10 @@ struct DevParams {
   float acc_scale;
   float out_inv_scale;
   int group_m;
+  int ldc;            // output row stride (elements)
+  const int* pos;     // EPI_ROPE: position of each row within its record
+  const float* rope;  // EPI_ROPE: [max_pos][64] cos (first 32) and sin (last 32)
+  int rope_cols;      // EPI_ROPE: columns below this are rotated
 };
 
 // The MFMAs take the weight fragment as their first operand, so each
@@ -136,7 +140,10 @@ struct DevParams {
 // the 32 rows a register quad spans land on distinct bank groups.
 template <typename TO, int EPI, int TM, int TN, int NW, int SMEM>
 struct Staging {
-  static constexpr int ROWB = TN * 32 * (int)sizeof(TO);        // bytes per staged row
+  // output columns of a wave: the gated epilogue writes one of each pair
+  // of 32-column sub-blocks
+  static constexpr int OTN = EPI == EPI_GEGLU ? TN / 2 : TN;
+  static constexpr int ROWB = OTN * 32 * (int)sizeof(TO);       // bytes per staged row
   static constexpr int CPR = ROWB / 16;                          // 16-byte chunks per row
   static constexpr int SWZ = (CPR < 16 ? CPR : 16) - 1;
   static constexpr int STRIP = 32 * ROWB;                        // one 32-row strip of one wave
@@ -186,6 +193,11 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
   typedef Staging<TO, EPI, TM, TN, NW, SMEM> SG;
   constexpr int ROWB = SG::ROWB, CPR = SG::CPR, SWZ = SG::SWZ, NS = SG::NS;
   const int M = p.M, N = p.N;
+  constexpr bool PAIRED = EPI == EPI_ROPE || EPI == EPI_GEGLU;
+  static_assert(!PAIRED || TN % 2 == 0, "paired epilogues need whole 64-column blocks per wave");
+  static_assert(EPI != EPI_GEGLU || sizeof(TO) >= 2, "the gated epilogue writes bf16 or fp32");
+  // where this wave's outputs start in a row of C
+  const int ocol0 = EPI == EPI_GEGLU ? wcol0 / 2 : wcol0;
   char* stg = smem + wave * NS * SG::STRIP;
   const int lrow = lane & 31, lq = (lane >> 5) * 4;
   // bias of the lane's columns (loaded before any store)
@@ -202,6 +214,58 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
       const int i = i0 + is;
       const int srow = is * 32 + lrow;  // staged row
       const int grow = min(wrow0 + i * 32 + lrow, M - 1);
+      if constexpr (PAIRED) {
+        // sub-blocks j and j+1 hold the two members of each pair: columns
+        // c and c + 32 of a 64-column head block (RoPE), or the input and
+        // the gate half of the gated MLP (weights interleaved in 32-column
+        // blocks)
+        int prow = 0;
+        if constexpr (EPI == EPI_ROPE) prow = p.pos[grow];
+#pragma unroll
+        for (int j = 0; j < TN; j += 2) {
+          const bool rot = EPI == EPI_ROPE && wcol0 + j * 32 < p.rope_cols;
+          const bool qs = EPI == EPI_ROPE && wcol0 + j * 32 < p.qcols;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int d0 = q * 8 + lq;  // index within the 32-column sub-block
+            float a[4], b[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              a[e] = acc[i][j][q * 4 + e] * p.acc_scale + bias[j][q][e];
+              b[e] = acc[i][j + 1][q * 4 + e] * p.acc_scale + bias[j + 1][q][e];
+            }
+            if constexpr (EPI == EPI_ROPE) {
+              if (rot) {
+                const floatx4 cs = *(const floatx4*)(p.rope + (size_t)prow * 64 + d0);
+                const floatx4 sn = *(const floatx4*)(p.rope + (size_t)prow * 64 + 32 + d0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const float x1 = a[e], x2 = b[e];
+                  a[e] = x1 * cs[e] - x2 * sn[e];
+                  b[e] = x2 * cs[e] + x1 * sn[e];
+                }
+              }
+              if (qs) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  a[e] *= p.qscale;
+                  b[e] *= p.qscale;
+                }
+              }
+              const int ba = (j * 32 + d0) * (int)sizeof(TO), bb = ((j + 1) * 32 + d0) * (int)sizeof(TO);
+              st4((TO*)(stg + srow * ROWB + (((ba >> 4) ^ (srow & SWZ)) * 16) + (ba & 15)), a);
+              st4((TO*)(stg + srow * ROWB + (((bb >> 4) ^ (srow & SWZ)) * 16) + (bb & 15)), b);
+            } else {
+              float y[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) y[e] = gelu_erf(a[e]) * b[e];
+              const int by = ((j / 2) * 32 + d0) * (int)sizeof(TO);
+              st4((TO*)(stg + srow * ROWB + (((by >> 4) ^ (srow & SWZ)) * 16) + (by & 15)), y);
+            }
+          }
+        }
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
 #pragma unroll
@@ -243,7 +307,7 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
       const int i = i0 + srow / 32;  // past TM only in a last, partial pass
       const int grow = wrow0 + i * 32 + (srow & 31);
       const intx4 v = *(const intx4*)(stg + srow * ROWB + ((cc ^ (srow & SWZ)) * 16));
-      if (i < TM && grow < M) *(intx4*)((char*)p.C + ((size_t)grow * N + wcol0) * sizeof(TO) + cc * 16) = v;
+      if (i < TM && grow < M) *(intx4*)((char*)p.C + ((size_t)grow * p.ldc + ocol0) * sizeof(TO) + cc * 16) = v;
     }
     if (i0 + NS < TM) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -585,6 +649,17 @@ struct Cfg {
   const char* name;
 };
 
+// Whether a tile serves an epilogue: the paired epilogues need an even
+// number of 32-column sub-blocks per wave, and one 32-row output strip per
+// wave must fit the kernel's LDS (mirrors Staging).
+constexpr bool staging_fits(int bm, int bn, int bk, int wgm, int wgn, int st, int in_bytes, int out_bytes, int epi) {
+  const int tn = bn / wgn / 32;
+  if ((epi == EPI_ROPE || epi == EPI_GEGLU) && tn % 2 != 0) return false;
+  const int smem = st == 0 ? 2 * (bm + bn) * (bk + 16 / in_bytes) * in_bytes : st * (bm + bn) * bk * in_bytes;
+  const int otn = epi == EPI_GEGLU ? tn / 2 : tn;
+  return smem >= wgm * wgn * 32 * otn * 32 * out_bytes;
+}
+
 // Tile configurations per input type; index = GemmParams::config.
 // Columns: BM, BN, BK, wave grid WGM x WGN, LDS ring stages (0: the
 // register-staged kernel), workgroups per CU the registers are sized for.
@@ -635,12 +710,16 @@ const Cfg* cfgs(ElemType t, int* n) {
 }
 
 template <typename TI, typename TO, typename TR, int EPI, int BM, int BN, int BK, int WGM, int WGN, int ST, int OCC>
-void run(const GemmParams& g, hipStream_t s) {
+bool run(const GemmParams& g, hipStream_t s) {
+  if constexpr (!staging_fits(BM, BN, BK, WGM, WGN, ST, (int)sizeof(TI), (int)sizeof(TO), EPI)) {
+    return false;  // no pairs in a wave's columns, or the output strips do not fit the LDS
+  } else {
   // tile order: by default, groups of 8 row blocks when a row block spans 8
   // or more column blocks (its weight panels would otherwise cycle through
   // the XCD's L2 once per row block), else plain row-major order
   const int gm = g.group_m > 0 ? g.group_m : (g.N / BN >= 8 ? 8 : 1);
-  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale, gm};
+  DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale, gm,
+              g.ldc > 0 ? g.ldc : (g.epi == EPI_GEGLU ? g.N / 2 : g.N), g.pos, g.rope, g.rope_cols};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
   if constexpr (ST == 0) {
     hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles),
@@ -650,12 +729,13 @@ void run(const GemmParams& g, hipStream_t s) {
     hipLaunchKernelGGL((gemm_dma_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, ST, OCC>), dim3(tiles),
                        dim3(WGM * WGN * 64), 0, s, p);
   }
+  return true;
+  }
 }
 
 #define ANON_CFG_CASE(i, bm, bn, bk, wgm, wgn, st, occ, name) \
   case i:                                                      \
-    run<TI, TO, TR, EPI, bm, bn, bk, wgm, wgn, st, occ>(g, s); \
-    return true;
+    return run<TI, TO, TR, EPI, bm, bn, bk, wgm, wgn, st, occ>(g, s);
 
 template <typename TI, typename TO, typename TR, int EPI>
 bool dispatch_tile(const GemmParams& g, int ci, hipStream_t s) {
@@ -677,7 +757,16 @@ bool dispatch_epi(const GemmParams& g, int ci, hipStream_t s) {
     if (g.epi == EPI_GELU && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GELU>(g, ci, s);
     if (g.epi == EPI_RESID && g.res == ET_F32 && g.out == ET_F32)
       return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
+    if (g.epi == EPI_ROPE && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_ROPE>(g, ci, s);
+    if (g.epi == EPI_GEGLU && g.out == ET_F32) return dispatch_tile<TI, float, float, EPI_GEGLU>(g, ci, s);
   } else {
+    if constexpr (sizeof(TI) == 2) {
+      // the ModernBERT-style encoder: rotary QKV, gated MLP, FP32 residual stream
+      if (g.epi == EPI_ROPE && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_ROPE>(g, ci, s);
+      if (g.epi == EPI_GEGLU && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GEGLU>(g, ci, s);
+      if (g.epi == EPI_RESID && g.res == ET_F32 && g.out == ET_F32)
+        return dispatch_tile<TI, float, float, EPI_RESID>(g, ci, s);
+    }
     if (g.epi == EPI_BIAS && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_BIAS>(g, ci, s);
     if constexpr (sizeof(TI) == 2) {
       if (g.epi == EPI_GELU && g.out == ET_BF16) return dispatch_tile<TI, bf16_t, float, EPI_GELU>(g, ci, s);
@@ -711,21 +800,31 @@ bool gemm_config_fits(ElemType in, int config, int N, int K) {
   return N % c[config].bn == 0 && K % c[config].bk == 0;
 }
 
+static int elem_bytes(ElemType t) { return t == ET_F32 ? 4 : (t == ET_BF16 ? 2 : 1); }
+
+bool gemm_config_serves(const GemmParams& g, int config) {
+  int n;
+  const Cfg* c = cfgs(g.in, &n);
+  if (!gemm_config_fits(g.in, config, g.N, g.K)) return false;
+  const Cfg& k = c[config];
+  return staging_fits(k.bm, k.bn, k.bk, k.wgm, k.wgn, k.st, elem_bytes(g.in), elem_bytes(g.out), g.epi);
+}
+
 int default_gemm_config(const GemmParams& g) {
-  // the preferred tile of the type if it divides the shape, else the first
-  // one that does
+  // the preferred tile of the type if it serves the shape and epilogue,
+  // else the first one that does
   const int n = gemm_num_configs(g.in);
   const int pref = g.in == ET_BF16 ? 11 : (g.in == ET_FP8 ? 7 : 0);
-  if (gemm_config_fits(g.in, pref, g.N, g.K)) return pref;
+  if (gemm_config_serves(g, pref)) return pref;
   for (int c = 0; c < n; ++c)
-    if (gemm_config_fits(g.in, c, g.N, g.K)) return c;
+    if (gemm_config_serves(g, c)) return c;
   return -1;
 }
 
 bool launch_gemm(const GemmParams& g, hipStream_t s) {
   int ci = g.config;
   if (ci < 0) ci = default_gemm_config(g);
-  if (ci < 0 || !gemm_config_fits(g.in, ci, g.N, g.K)) {
+  if (ci < 0 || !gemm_config_serves(g, ci)) {
     set_error(ANON_EINVAL, "gemm: no tile configuration divides N=" + std::to_string(g.N) + " K=" +
                                std::to_string(g.K));
     return false;

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
                                                        const float* __restrict__ pos, const float* __restrict__ g,
                                                        const float* __restrict__ b, float eps, int vocab,
                                                        int max_pos, void* out, ElemType out_t, fp8_t* out_q,
-                                                       float q_inv_scale, uint32_t* err) {
+                                                       float q_inv_scale, int* pos_out, uint32_t* err) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
@@ -140,11 +140,15 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
   }
   const int r = find_record(cu, B, t);
   const int p = min(max(t - cu[r], 0), max_pos - 1);
-  float v[NPL], w[NPL];
+  if (pos_out && lane == 0) pos_out[t] = p;
+  float v[NPL];
   load_row<NPL>(tok + (size_t)id * h, lane, v);
-  load_row<NPL>(pos + (size_t)p * h, lane, w);
+  if (pos) {  // learned absolute positions (no table: positions enter elsewhere)
+    float w[NPL];
+    load_row<NPL>(pos + (size_t)p * h, lane, w);
 #pragma unroll
-  for (int i = 0; i < NPL; ++i) v[i] += w[i];
+    for (int i = 0; i < NPL; ++i) v[i] += w[i];
+  }
   float gv[NPL], bv[NPL];
   load_row<NPL>(g, lane, gv);
   load_row<NPL>(b, lane, bv);
@@ -288,6 +292,15 @@ __global__ void to_f32_kernel(const TX* __restrict__ x, float* __restrict__ out,
   if (i < n) out[i] = ldf(x + i);
 }
 
+// FP32 -> bf16, four elements per thread (n a multiple of 4)
+__global__ void f32_to_bf16_kernel(const float* __restrict__ x, bf16_t* __restrict__ out, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const floatx4 v = *(const floatx4*)(x + 4 * i);
+  *(bf16x4*)(out + 4 * i) = bf16x4{static_cast<bf16_t>(v[0]), static_cast<bf16_t>(v[1]), static_cast<bf16_t>(v[2]),
+                                   static_cast<bf16_t>(v[3])};
+}
+
 // dst[c][r] = src[r][c] * inv_scale, converted to the storage type.
 template <typename TD>
 __global__ __launch_bounds__(256) void transpose_convert_kernel(const float* __restrict__ src, int rows, int cols,
@@ -378,11 +391,17 @@ __global__ void fill_random_kernel(void* p, ElemType t, int64_t n, uint32_t seed
 
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
                      const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
-                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s) {
+                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s, int* pos_out) {
   if (T <= 0) return;
   ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((embed_ln_kernel<NPL>), dim3(ceil_div(T, 4)), dim3(256), 0, s, ids,
                                              cu_seqlens, B, T, tok_emb, pos_emb, g, b, eps, vocab, max_pos, out,
-                                             out_t, out_q, q_inv_scale, err));
+                                             out_t, out_q, q_inv_scale, pos_out, err));
+}
+
+void launch_f32_to_bf16(const float* x, bf16_t* out, int64_t n, hipStream_t s) {
+  const int64_t n4 = n / 4;
+  if (n4 <= 0) return;
+  hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, x, out, n4);
 }
 
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,

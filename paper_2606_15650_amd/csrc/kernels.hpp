@@ -6,7 +6,10 @@
 namespace anon {
 
 // ---- GEMM: C[M,N] = A[M,K] * W[N,K]^T with a fused epilogue --------------
-enum GemmEpi { EPI_BIAS = 0, EPI_GELU = 1, EPI_RESID = 2 };
+// EPI_ROPE: bias, rotary rotation of the pairs (c, c+32) of each 64-column
+// head block below rope_cols by the row's position, Q scaling.  EPI_GEGLU:
+// GELU(u) * g of the interleaved 32-column blocks u, g (output N/2 wide).
+enum GemmEpi { EPI_BIAS = 0, EPI_GELU = 1, EPI_RESID = 2, EPI_ROPE = 3, EPI_GEGLU = 4 };
 enum ElemType { ET_F32 = 0, ET_BF16 = 1, ET_FP8 = 2 };
 
 struct GemmParams {
@@ -24,6 +27,10 @@ struct GemmParams {
   GemmEpi epi;
   int config;         // tile configuration index (-1: default choice)
   int group_m;        // row blocks per tile group (0: chosen by shape; 1: row-major)
+  int ldc;            // output row stride (0: N, or N/2 for EPI_GEGLU)
+  const int* pos;     // EPI_ROPE: [M] position of each row within its record
+  const float* rope;  // EPI_ROPE: [positions][64] cos (first 32), sin (last 32)
+  int rope_cols;      // EPI_ROPE: columns below this are rotated
 };
 // Returns false (and sets the error) if no kernel matches the shapes/types.
 bool launch_gemm(const GemmParams& p, hipStream_t s);
@@ -31,6 +38,9 @@ int default_gemm_config(const GemmParams& p);
 int gemm_num_configs(ElemType in);
 const char* gemm_config_name(ElemType in, int config);
 bool gemm_config_fits(ElemType in, int config, int N, int K);
+// the configuration divides the shape and, for the paired epilogues, gives
+// each wave whole 64-column blocks
+bool gemm_config_serves(const GemmParams& p, int config);
 
 // ---- attention ------------------------------------------------------------
 // Work list of the attention kernel (validates cu_seqlens on the device).
@@ -42,14 +52,19 @@ const char* attn_config_name(int config);
 int attn_plan_items(ElemType t, int config, int T, int B);
 void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int config, int4* items,
                       int max_items, int* n_items, uint32_t* err, hipStream_t s);
+// window > 0: query i sees only keys j with |i - j| <= window
 void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* n_items,
                       int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale, int config,
-                      hipStream_t s);
+                      hipStream_t s, int window = 0);
 
 // ---- row-wise kernels -----------------------------------------------------
+// pos_emb may be null (no learned positions); pos_out (nullable) receives
+// each token's position within its record
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
                      const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
-                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s);
+                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s,
+                     int* pos_out = nullptr);
+void launch_f32_to_bf16(const float* x, bf16_t* out, int64_t n, hipStream_t s);
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
                       void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s);
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,

@@ -32,12 +32,14 @@ LOGIT_BOUND = {("bf16", 2): 5e-3, ("fp8", 2): 5e-3, ("bf16", 12): _probe_bound("
 PERTURB_SEEDS = (1, 2, 3)
 
 
-def oracle_ner(W, cfg, ids, cu_seqlens, make_prec=None, window: int = 0, stride: int = 0, workers: int | None = None):
+def oracle_ner(W, cfg, ids, cu_seqlens, make_prec=None, window: int = 0, stride: int = 0, workers: int | None = None,
+               forward=None):
     """The oracle's NER (logits, labels, margins) over a packed batch, with its
     records split into contiguous groups of about equal token counts that run
     in parallel threads (numpy releases the GIL in its array work).  Each
     group is a packed batch of its own: the oracle's result for a record does
-    not depend on its batch-mates (pinned on the CPU).  ``make_prec(g)`` gives
+    not depend on its batch-mates (pinned on the CPU).  ``forward`` replaces
+    the BERT-style oracle (e.g. oracle.modernbert.forward).  ``make_prec(g)`` gives
     group g its Precision (a fresh one per group, so that a stateful reading
     such as the perturbed one draws from its own stream)."""
     from concurrent.futures import ThreadPoolExecutor
@@ -62,13 +64,15 @@ def oracle_ner(W, cfg, ids, cu_seqlens, make_prec=None, window: int = 0, stride:
             bounds.append(r)
     bounds.append(B)
 
+    ner = forward or (lambda W_, c_, i_, cu_, p_: opipe.ner(W_, c_, i_, cu_, p_, window, stride))
+
     def run(g):
         a, b = bounds[g], bounds[g + 1]
         sub_cu = cu[a:b + 1] - cu[a]
-        return opipe.ner(W, cfg, ids[cu[a]:cu[b]], sub_cu, make_prec(g), window, stride)
+        return ner(W, cfg, ids[cu[a]:cu[b]], sub_cu, make_prec(g))
 
     if B == 0:
-        return opipe.ner(W, cfg, ids, cu, make_prec(0), window, stride)
+        return ner(W, cfg, ids, cu, make_prec(0))
     with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
         parts = list(ex.map(run, range(len(bounds) - 1)))
     z = np.concatenate([p[0] for p in parts])

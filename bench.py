@@ -75,6 +75,127 @@ def path_flops(cfg, cu: np.ndarray) -> float:
     return cfg.n_layers * (g * T + attention_flops(cu, cfg)) + 2.0 * cfg.hidden * cfg.n_labels * T
 
 
+def modern_flops(cfg, cu: np.ndarray) -> dict:
+    """Algorithmic FLOPs of one pass of the ModernBERT-style encoder, per
+    kernel class: the GEMMs per token, attention from the pairs each query
+    sees (all keys of its record on global layers, those at most
+    local_window/2 away on local ones), the head and classifier."""
+    h, I = cfg.hidden, cfg.intermediate
+    T = float(cu[-1])
+    L = np.diff(cu).astype(np.int64)
+    w = cfg.local_window // 2
+    full = float((L.astype(np.float64) ** 2).sum())
+    # pairs |i - j| <= w in a record of n tokens
+    n = L.astype(np.float64)
+    ww = np.minimum(w, n - 1)
+    band = float((n * (2 * ww + 1) - ww * (ww + 1)).sum())
+    n_glob = sum(1 for l in range(cfg.n_layers) if l % cfg.global_every == 0)
+    att = 4.0 * h * (n_glob * full + (cfg.n_layers - n_glob) * band)
+    gl = cfg.n_layers
+    return {"qkv": gl * 2.0 * h * 3 * h * T, "oproj": gl * 2.0 * h * h * T, "ffn1": gl * 2.0 * h * 2 * I * T,
+            "ffn2": gl * 2.0 * I * h * T, "attn": att, "cls": 2.0 * h * h * T + 2.0 * h * cfg.n_labels * T}
+
+
+def modern_bench(steps: int, warmup: int, keep: bool, log=None) -> dict:
+    """The ModernBERT-style encoder (22 layers, h768, GeGLU 1152, local and
+    global attention) on the base workload's records: the whole path (NER,
+    spans, pseudonyms) timed like the headline, its kernels, the dominant
+    kernel against the BF16 MFMA peak."""
+    import torch
+
+    import synth
+    from paper_2606_15650_amd import api
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline
+
+    wl = synth.workload("modern_bf16")
+    cfg = wl.model
+    rb = synth.generate_records(wl.n_records, wl.lengths, cfg.n_types, cfg.vocab, wl.seed)
+    W = synth.make_weights(cfg, wl.weight_seed, wl.o_target)
+    key = synth.make_key(0)
+    model = api.ModernModel(cfg, synth.weights_blob(cfg, W), "bf16")
+    cache = api.PseudonymCache(key, 10, rb.type_names, 1 << 20)
+    pl = Pipeline(model, cache)
+    db = DeviceBatch(rb)
+    T = rb.n_tokens
+    for _ in range(warmup):
+        pl.step(db)
+    torch.cuda.synchronize()
+    classes = ["qkv", "attn", "oproj", "ffn1", "ffn2", "ln", "embed", "cls"]
+    for k in classes:
+        api.prof_enable(k, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.step(db)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = {k: api.prof_read(k) for k in classes}
+    for k in classes:
+        api.prof_enable(k, False)
+    fl = modern_flops(cfg, rb.cu_seqlens.astype(np.int64))
+    breakdown = {}
+    for k, v in kern.items():
+        if v["launches"]:
+            f = fl.get(k)
+            per_launch = f / (v["launches"] / steps) if f else None
+            breakdown[k] = {"launches": v["launches"], "ms_per_step": v["ms"] / steps,
+                            "tflops": (per_launch * v["launches"] / (v["ms"] * 1e-3) / 1e12) if f else None}
+    dom = max((k for k in breakdown if fl.get(k)), key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    avg_ms = d["ms"] / d["launches"]
+    per_launch = fl[dom] / (d["launches"] / steps)
+    total = sum(fl.values())
+    out = {"workload": wl.name, "value": T * steps / wall, "unit": "tokens/s", "ms_per_step": wall / steps * 1e3,
+           "steps": steps, "dtype": "bf16",
+           "config": {"records": rb.n_records, "tokens": T, "layers": cfg.n_layers, "hidden": cfg.hidden,
+                      "heads": cfg.n_heads, "intermediate": cfg.intermediate, "vocab": cfg.vocab,
+                      "local_window": cfg.local_window, "global_every": cfg.global_every,
+                      "lengths": list(wl.lengths)},
+           "roofline": {"bound": "mfma", "kernel": dom, "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
+                        "peak": PEAK_FLOPS["bf16"] / 1e12, "unit": "TFLOP/s",
+                        "frac": per_launch / (avg_ms * 1e-3) / PEAK_FLOPS["bf16"], "avg_launch_ms": avg_ms,
+                        "flops_per_launch": per_launch},
+           "path_tflops": total / (wall / steps) / 1e12, "path_mfma_frac": total / (wall / steps) / PEAK_FLOPS["bf16"],
+           "kernels": breakdown, "pcache": cache.stats()}
+    ctx = None
+    if keep:
+        _, z, _ = pl.ner(db, logits=True)
+        torch.cuda.synchronize()
+        ctx = {"wl": wl, "rb": rb, "W": W, "z": z[:T].cpu().numpy()}
+    model.close()
+    cache.close()
+    return out, ctx
+
+
+def modern_parity(ctx: dict, budget_s: float) -> dict:
+    """Logit error and label agreement of the ModernBERT-style path on its
+    first records against the pure FP64 oracle and the rounding oracle (part
+    of the CPU baseline leg)."""
+    from oracle import encoder, modernbert as mb
+    wl, rb, W, zg_all = ctx["wl"], ctx["rb"], ctx["W"], ctx["z"]
+    cfg = wl.model
+    zs, zqs, nrec = [], [], 0
+    t0 = time.perf_counter()
+    while nrec < rb.n_records and time.perf_counter() - t0 < budget_s:
+        sub = rb.subset([nrec])
+        zs.append(mb.forward(W, cfg, sub.ids, sub.cu_seqlens)[0])
+        zqs.append(mb.forward(W, cfg, sub.ids, sub.cu_seqlens, encoder.Precision("bf16"))[0])
+        nrec += 1
+    n = int(rb.cu_seqlens[nrec])
+    zg = zg_all[:n].astype(np.float64)
+    lg = encoder.argmax_margin(zg)[0]
+    out = {"records": nrec, "tokens": n}
+    for name, zr in (("vs_pure_fp64_oracle", np.concatenate(zs)), ("vs_rounding_oracle", np.concatenate(zqs))):
+        lr, mr = encoder.argmax_margin(zr)
+        d = np.abs(zg - zr)
+        conf = mr > 1e-2
+        out[name] = {"max_abs_logit_err": float(d.max()), "rms_logit_err": float(np.sqrt((d ** 2).mean())),
+                     "label_agreement_all": float((lg == lr).mean()),
+                     "label_agreement_confident": float((lg[conf] == lr[conf]).mean()) if conf.any() else 1.0,
+                     "confident_label_mismatches": int((conf & (lg != lr)).sum()),
+                     "tokens_margin_le_1e-2": int((~conf).sum())}
+    return out
+
+
 def cpu_baseline(wl, rb, W, key, budget_s: float = 12.0):
     """The FP64 oracle on the first records of the workload, until ~budget_s of
     CPU work.  Returns the baseline entry and the oracle's logits, labels and
@@ -419,6 +540,7 @@ def main() -> int:
     ap.add_argument("--no-recognizers", action="store_true",
                     help="skip the timings of the recognizer and schema-field paths")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 path on the large workload")
+    ap.add_argument("--no-modern", action="store_true", help="skip the ModernBERT-style encoder's path")
     ap.add_argument("--fp8-steps", type=int, default=3)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -681,6 +803,10 @@ def main() -> int:
                           "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tokens_per_s": r["tokens_per_s"],
                           "offered_tokens_per_s": r["offered_tokens_per_s"], "failed": r["failed"],
                           "seconds": 6.0, "config": sv["config"]}
+    mctx = None
+    if not a.no_modern and a.workload == "base_bf16":
+        print("[bench] ModernBERT-style path", file=sys.stderr, flush=True)
+        out["modernbert_path"], mctx = modern_bench(max(2, a.steps // 2), 1, keep=not a.no_cpu)
     fp8 = None
     if not a.no_fp8 and a.workload == "base_bf16":
         # the FP8-E4M3 path on its own workload (24 layers, h1024), a few steps
@@ -693,6 +819,8 @@ def main() -> int:
         base, pure = cpu_baseline(ctx["wl"], ctx["rb"], ctx["W"], ctx["key"], a.cpu_budget)
         out["cpu_baseline"] = base
         out["parity"] = parity_leg(ctx["wl"], ctx["rb"], ctx["W"], pure, ctx["gpu"], ctx["scales"])
+        if mctx is not None:
+            out["modernbert_path"]["parity"] = modern_parity(mctx, a.cpu_budget / 2)
         if fp8 is not None:
             # a short sample of the FP8 workload (24-layer oracle: a few records)
             _, fpure = cpu_baseline(fctx["wl"], fctx["rb"], fctx["W"], fctx["key"], a.cpu_budget / 3)

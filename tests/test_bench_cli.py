@@ -37,3 +37,20 @@ def test_flop_counts_match_the_encoder_closed_form():
     assert bench.attention_flops(cu3, BASE) == 4 * h * (10 ** 2 + 0 + 30 ** 2)
     g = bench.gemm_flops_per_token(BASE)
     assert g["qkv"] == 3 * g["oproj"] and g["ffn1"] == g["ffn2"] == 2 * h * f
+
+
+def test_modern_attention_flops_count_the_window_pairs():
+    """The ModernBERT-style FLOP accounting: attention counts every key a
+    query sees (all of its record on global layers, those at most 64 positions
+    away on local ones), checked against a brute-force pair count."""
+    import numpy as np
+    import bench
+    from synth.configs import MODERN_BASE
+    cu = np.array([0, 3, 100, 700, 829])
+    f = bench.modern_flops(MODERN_BASE, cu)
+    L = np.diff(cu)
+    band = sum(sum(1 for i in range(n) for j in range(n) if abs(i - j) <= 64) for n in L)
+    full = sum(int(n) * int(n) for n in L)
+    n_glob = len(range(0, MODERN_BASE.n_layers, MODERN_BASE.global_every))
+    assert f["attn"] == 4 * MODERN_BASE.hidden * (n_glob * full + (MODERN_BASE.n_layers - n_glob) * band)
+    assert f["ffn1"] == MODERN_BASE.n_layers * 2 * 768 * 2 * 1152 * 829

@@ -369,7 +369,7 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, s
                        "streams": streams}, "rates": results}
 
 
-def stream_bench(max_chunk_tokens: int = 2_000_000) -> dict:
+def stream_bench(max_chunk_tokens: int = 2_000_000, warm_chunks: int | None = None) -> dict:
     """Dataset-scale streaming workload: 70,951 records (~550 MB) windowed at
     512 tokens with 64-token overlap, processed in chunks with every input
     resident in HBM and one pseudonym table across chunks."""
@@ -415,9 +415,9 @@ def stream_bench(max_chunk_tokens: int = 2_000_000) -> dict:
     class Chunk:
         pass
 
-    def run(stream_pass: bool):
+    def run(stream_pass: bool, n_chunks: int | None = None):
         n_spans = 0
-        for k, (a, b) in enumerate(chunks):
+        for k, (a, b) in enumerate(chunks[:n_chunks]):
             c = Chunk()
             c.B, c.T = b - a, int(cu[b] - cu[a])
             c.n_bytes = int(cb[b] - cb[a])
@@ -435,7 +435,7 @@ def stream_bench(max_chunk_tokens: int = 2_000_000) -> dict:
                       file=sys.stderr, flush=True)
         return n_spans
 
-    run(False)  # warm-up pass (fills the pseudonym table as a first pass would)
+    run(False, warm_chunks)  # warm-up (the table is cleared before the timed pass)
     cache.clear()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -541,6 +541,7 @@ def main() -> int:
                     help="skip the timings of the recognizer and schema-field paths")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 path on the large workload")
     ap.add_argument("--no-modern", action="store_true", help="skip the ModernBERT-style encoder's path")
+    ap.add_argument("--no-stream", action="store_true", help="skip the dataset-scale stream")
     ap.add_argument("--fp8-steps", type=int, default=3)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -795,14 +796,22 @@ def main() -> int:
     out, ctx = path_bench(a.workload, a.steps, a.warmup, extras=not a.no_recognizers, fp32=not a.no_fp32,
                           keep_logits=not a.no_cpu)
     if not a.no_serve and a.workload == "base_bf16":
-        # request latency under streaming load (the serving workload at one
-        # rate, short); `--serve RATES` runs the full sweep
-        sv = serve_bench([100.0], 6.0, 1.5, log=sys.stderr)
-        r = sv["rates"][0]
-        out["serving"] = {"workload": sv["workload"], "rate_req_s": r["rate_req_s"], "requests": r["requests"],
-                          "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "tokens_per_s": r["tokens_per_s"],
-                          "offered_tokens_per_s": r["offered_tokens_per_s"], "failed": r["failed"],
-                          "seconds": 6.0, "config": sv["config"]}
+        # request latency under streaming load: the serving workload at three
+        # rates, 8 s of arrivals each after 1.5 s of warm-up; `--serve RATES`
+        # runs any sweep
+        sv = serve_bench([50.0, 100.0, 200.0], 8.0, 1.5, log=sys.stderr)
+        out["serving"] = {"workload": sv["workload"], "seconds_per_rate": 8.0, "config": sv["config"],
+                          "rates": [{k: r[k] for k in ("rate_req_s", "requests", "p50_ms", "p99_ms", "mean_ms",
+                                                       "tokens_per_s", "offered_tokens_per_s", "failed")}
+                                    for r in sv["rates"]]}
+    if not a.no_stream and a.workload == "base_bf16":
+        # the dataset-scale stream (70,951 records, 554 MB, windows of 512
+        # every 448): one timed pass over the whole dataset
+        print("[bench] dataset-scale stream", file=sys.stderr, flush=True)
+        st = stream_bench(warm_chunks=1)
+        out["stream_path"] = {k: st[k] for k in ("value", "unit", "wall_s", "config", "pcache_predicted_spans",
+                                                 "pcache_gold_spans", "schema_fields", "recognizers_only",
+                                                 "input_gen_s", "paper_context")}
     mctx = None
     if not a.no_modern and a.workload == "base_bf16":
         print("[bench] ModernBERT-style path", file=sys.stderr, flush=True)

@@ -268,6 +268,8 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
+        // the Q columns are whole 32-column blocks (qcols is a multiple of 64)
+        const bool qs = EPI == EPI_BIAS && wcol0 + j * 32 < p.qcols;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int cl = j * 32 + q * 8 + lq;  // column within the wave's block
@@ -279,7 +281,7 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
           for (int e = 0; e < 4; ++e) {
             float x = acc[i][j][q * 4 + e] * p.acc_scale + bias[j][q][e];
             if (EPI == EPI_BIAS) {
-              if (col + e < p.qcols) x *= p.qscale;
+              if (qs) x *= p.qscale;
             } else if (EPI == EPI_GELU) {
               x = gelu_erf(x);
               // FP8 output: the activation is a bf16 value first (as in the
@@ -827,6 +829,10 @@ bool launch_gemm(const GemmParams& g, hipStream_t s) {
   if (ci < 0 || !gemm_config_serves(g, ci)) {
     set_error(ANON_EINVAL, "gemm: no tile configuration divides N=" + std::to_string(g.N) + " K=" +
                                std::to_string(g.K));
+    return false;
+  }
+  if ((g.epi == EPI_BIAS || g.epi == EPI_ROPE) && (g.qcols % 64 != 0 || g.rope_cols % 64 != 0)) {
+    set_error(ANON_EINVAL, "gemm: scaled and rotated columns must be whole 64-column blocks");
     return false;
   }
   if (g.M <= 0) return true;

@@ -278,13 +278,14 @@ def parity_leg(wl, rb, W, pure: dict, gpu: dict, scales=None) -> dict:
 
 
 def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, streams: int = 3,
-                max_tok: int = 131072) -> dict:
+                max_tok: int = 131072, graph_buckets: int = 8) -> dict:
     """Continuous-batching server under Poisson arrivals (serving workload).
 
     Requests hold U{1..200} records with the base workload's length
     distribution (drawn from a generated pool of records); arrivals are
     Poisson at each rate for `seconds` after `warm_s` of warm-up traffic.
-    Latency = completion - submission per request.
+    Latency = completion - submission per request.  With graph_buckets > 0
+    every micro-batch's NER forward is one replay of a token-bucket graph.
     """
     import threading
 
@@ -302,7 +303,7 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, s
     results = []
     for rate in rates:
         sv = api.Server(model, cache, hbm_budget_bytes=64 << 30, max_batch_tokens=max_tok, n_streams=streams,
-                        max_queue=100000)
+                        max_queue=100000, graph_buckets=graph_buckets)
         rng = np.random.default_rng(seed + int(rate))
         # request = a run of consecutive pool records (wrapping), U{1..200} long
         reqs = []
@@ -349,6 +350,7 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, s
         stop.set()
         th.join()
         wall = time.perf_counter() - t0
+        sst = sv.stats()
         sv.stop()
         meas = [d for d in done if d[0] >= warm_s and d[4] == 0]
         lat = np.array([d[2] - d[1] for d in meas]) * 1e3
@@ -359,14 +361,15 @@ def serve_bench(rates, seconds: float, warm_s: float, seed: int = 0, log=None, s
         results.append({"rate_req_s": rate, "requests": len(meas), "p50_ms": float(np.percentile(lat, 50)),
                         "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                         "tokens_per_s": tok / (t_last - t_first), "offered_tokens_per_s": offered,
-                        "failed": sum(1 for d in done if d[4] != 0), "wall_s": wall})
+                        "failed": sum(1 for d in done if d[4] != 0), "wall_s": wall,
+                        "micro_batches": sst["micro_batches"], "graph_launches": sst["graph_launches"]})
         print(json.dumps({"serve_partial": results[-1]}), file=log or sys.stdout, flush=True)
     model.close()
     cache.close()
     return {"metric": "serving p50/p99 request latency", "unit": "ms", "workload": "serve_bf16",
             "config": {"model": "12L h768 BF16", "requests": "Poisson arrivals, U{1..200} records each, "
                        "lengths as base_bf16", "hbm_budget": "64 GiB", "max_batch_tokens": max_tok,
-                       "streams": streams}, "rates": results}
+                       "streams": streams, "graph_buckets": graph_buckets}, "rates": results}
 
 
 def stream_bench(max_chunk_tokens: int = 2_000_000, warm_chunks: int | None = None) -> dict:
@@ -534,6 +537,8 @@ def main() -> int:
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=3, help="server slots (HIP streams)")
     ap.add_argument("--serve-max-tokens", type=int, default=131072, help="tokens per micro-batch at most")
+    ap.add_argument("--serve-graphs", type=int, default=8,
+                    help="token-bucket graphs per server slot (0: launch the forward kernel by kernel)")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving run (100 req/s) of the default line")
@@ -551,7 +556,7 @@ def main() -> int:
     if a.serve:
         rates = [float(x) for x in a.serve.split(",")]
         print(json.dumps(serve_bench(rates, a.serve_seconds, a.serve_warmup, streams=a.serve_streams,
-                                     max_tok=a.serve_max_tokens)), flush=True)
+                                     max_tok=a.serve_max_tokens, graph_buckets=a.serve_graphs)), flush=True)
         return 0
     if a.workload == "stream_bf16":
         print(json.dumps(stream_bench()), flush=True)
@@ -797,13 +802,16 @@ def main() -> int:
                           keep_logits=not a.no_cpu)
     if not a.no_serve and a.workload == "base_bf16":
         # request latency under streaming load: the serving workload at three
-        # rates, 8 s of arrivals each after 1.5 s of warm-up; `--serve RATES`
-        # runs any sweep
-        sv = serve_bench([50.0, 100.0, 200.0], 8.0, 1.5, log=sys.stderr)
-        out["serving"] = {"workload": sv["workload"], "seconds_per_rate": 8.0, "config": sv["config"],
-                          "rates": [{k: r[k] for k in ("rate_req_s", "requests", "p50_ms", "p99_ms", "mean_ms",
-                                                       "tokens_per_s", "offered_tokens_per_s", "failed")}
-                                    for r in sv["rates"]]}
+        # rates, 10 s of arrivals each after 1.5 s of warm-up, forward passes
+        # as token-bucket graph replays; the middle rate again with kernel-by-
+        # kernel launches; `--serve RATES` runs any sweep
+        keys = ("rate_req_s", "requests", "p50_ms", "p99_ms", "mean_ms", "tokens_per_s", "offered_tokens_per_s",
+                "failed", "micro_batches", "graph_launches")
+        sv = serve_bench([50.0, 100.0, 200.0], 10.0, 1.5, log=sys.stderr, graph_buckets=8)
+        ev = serve_bench([100.0], 10.0, 1.5, log=sys.stderr, graph_buckets=0)
+        out["serving"] = {"workload": sv["workload"], "seconds_per_rate": 10.0, "config": sv["config"],
+                          "rates": [{k: r[k] for k in keys} for r in sv["rates"]],
+                          "eager_launches": [{k: r[k] for k in keys} for r in ev["rates"]]}
     if not a.no_stream and a.workload == "base_bf16":
         # the dataset-scale stream (70,951 records, 554 MB, windows of 512
         # every 448): one timed pass over the whole dataset

@@ -147,6 +147,25 @@ typedef struct anon_graph anon_graph;
 anon_status ner_forward_capture(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
                                 int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
                                 size_t ws_bytes, anon_graph** out);
+/* The same graph for a token bucket: any batch of at most B_cap records and
+ * T_cap tokens.  Every kernel of the graph reads the batch's token count
+ * from d_n_tokens (int32, device) when it runs; its grid covers T_cap rows
+ * and the rows at or past the count are neither computed nor written.  To
+ * run a batch of B <= B_cap records and T <= T_cap tokens, write its ids to
+ * d_ids[0 .. T), its boundaries to d_cu_seqlens[0 .. B] and
+ * d_cu_seqlens[b] = T for b in (B, B_cap] (empty records), T to
+ * *d_n_tokens, then launch; labels, logits and margins of tokens 0 .. T-1
+ * equal ner_forward's on that batch bit for bit.  A count outside
+ * [0, T_cap] or a d_cu_seqlens[B_cap] that differs from it raises the
+ * sequence-length bit of the device error word (the count is clamped, the
+ * outputs are then unspecified).  d_workspace >=
+ * anon_ner_workspace_size(T_cap, B_cap) bytes; ownership and races as for
+ * ner_forward_capture.  Serving replays one such graph per bucket
+ * (anon_server_config.graph_buckets). */
+anon_status ner_forward_capture_bucket(anon_model* model, const int32_t* d_ids, const int32_t* d_cu_seqlens,
+                                       const int32_t* d_n_tokens, int32_t B_cap, int32_t T_cap, uint8_t* d_labels,
+                                       float* d_logits, float* d_margin, void* d_workspace, size_t ws_bytes,
+                                       anon_graph** out);
 anon_status anon_graph_launch(anon_graph* graph, void* stream);
 void anon_graph_free(anon_graph* graph);
 
@@ -463,13 +482,24 @@ anon_status pseudonymize(anon_pcache* cache, const uint8_t* d_text, const int64_
  * still refuses (ANON_ECAPACITY) any request whose footprint alone exceeds
  * the arena.  A finished request's status is ANON_EDATA when its
  * micro-batch raised a device-data error bit (each micro-batch has its own
- * error word; requests that pass anon_submit's checks do not raise any). */
+ * error word; requests that pass anon_submit's checks do not raise any).
+ * With graph_buckets > 0 each slot also holds fixed forward buffers for a
+ * full micro-batch (ids, boundaries, token count, labels, error word, NER
+ * workspace), taken from the budget before the arena, and runs the NER
+ * forward as one graph launch of the smallest bucket that holds the
+ * micro-batch; the graphs are captured at start with the model's tile
+ * configuration of that moment.  Results are the same in both modes. */
 typedef struct {
   int64_t hbm_budget_bytes;   /* activation budget (e.g. 64 GiB)           */
   int32_t max_batch_tokens;   /* tokens per micro-batch                    */
   int32_t n_streams;          /* micro-batches in flight (1..8)            */
   int32_t max_queue;          /* queued requests before anon_submit EBUSY  */
   int32_t max_request_tokens; /* larger requests are rejected (EINVAL)     */
+  int32_t graph_buckets;      /* 0: the NER forward is launched kernel by
+                               * kernel; n in 1..16: each slot replays a HIP
+                               * graph of it per token bucket (n buckets:
+                               * max_batch_tokens, then halving; see
+                               * ner_forward_capture_bucket) */
 } anon_server_config;
 
 /* One request: n_records records with host arrays (copied before return). */
@@ -502,12 +532,14 @@ anon_status anon_submit(anon_server* server, const anon_request* req, uint64_t* 
 anon_status anon_poll(anon_server* server, uint64_t ticket, anon_result* out);
 anon_status anon_release(anon_server* server, uint64_t ticket);
 /* Counters since start: the arena size, the most arena bytes in use at once,
- * micro-batches launched and the most micro-batches in flight at once. */
+ * micro-batches launched, the most micro-batches in flight at once and the
+ * forward passes run as graph replays. */
 typedef struct {
   int64_t arena_bytes;
   int64_t peak_arena_bytes;
   int64_t micro_batches;
   int32_t max_concurrent;
+  int64_t graph_launches;
 } anon_server_counters;
 anon_status anon_server_stats(anon_server* server, anon_server_counters* out);
 /* Finishes in-flight work, fails queued requests, joins the thread. */

@@ -51,7 +51,7 @@ SPAN_BYTES = C.sizeof(SpanC)  # 24
 
 class ServerConfigC(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_batch_tokens", C.c_int32), ("n_streams", C.c_int32),
-                ("max_queue", C.c_int32), ("max_request_tokens", C.c_int32)]
+                ("max_queue", C.c_int32), ("max_request_tokens", C.c_int32), ("graph_buckets", C.c_int32)]
 
 
 class RequestC(C.Structure):
@@ -62,7 +62,7 @@ class RequestC(C.Structure):
 
 class ServerCountersC(C.Structure):
     _fields_ = [("arena_bytes", C.c_int64), ("peak_arena_bytes", C.c_int64), ("micro_batches", C.c_int64),
-                ("max_concurrent", C.c_int32)]
+                ("max_concurrent", C.c_int32), ("graph_launches", C.c_int64)]
 
 
 class ResultC(C.Structure):
@@ -84,6 +84,7 @@ _SIGS = {
     "ner_forward": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_encoder_hidden": ([vp, vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
     "ner_forward_capture": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
+    "ner_forward_capture_bucket": ([vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, C.POINTER(vp)], i32),
     "anon_graph_launch": ([vp, vp], i32),
     "anon_graph_free": ([vp], None),
     "anon_ner_windowed_workspace_size": ([vp, vp, i32, i32, i32, C.POINTER(sz)], i32),
@@ -364,6 +365,17 @@ def ner_forward_capture(model: Model, d_ids, d_cu_seqlens, B: int, T: int, d_lab
     return ForwardGraph(h.value, (model, d_ids, d_cu_seqlens, d_labels, d_logits, d_margin, d_workspace))
 
 
+def ner_forward_capture_bucket(model: Model, d_ids, d_cu_seqlens, d_n_tokens, B_cap: int, T_cap: int, d_labels,
+                               d_logits=None, d_margin=None, d_workspace=None, ws_bytes: int = 0) -> ForwardGraph:
+    h = vp()
+    _check("ner_forward_capture_bucket",
+           lib().ner_forward_capture_bucket(model.handle, ptr(d_ids), ptr(d_cu_seqlens), ptr(d_n_tokens), B_cap,
+                                            T_cap, ptr(d_labels), ptr(d_logits), ptr(d_margin), ptr(d_workspace),
+                                            ws_bytes, C.byref(h)))
+    return ForwardGraph(h.value, (model, d_ids, d_cu_seqlens, d_n_tokens, d_labels, d_logits, d_margin,
+                                  d_workspace))
+
+
 def encoder_hidden(model: Model, d_ids, d_cu_seqlens, B: int, T: int, n_layers: int, d_hidden, d_workspace,
                    ws_bytes: int, stream=None):
     _check("anon_encoder_hidden", lib().anon_encoder_hidden(model.handle, ptr(d_ids), ptr(d_cu_seqlens), B, T,
@@ -549,8 +561,9 @@ class Server:
 
     def __init__(self, model: Model, cache: PseudonymCache, hbm_budget_bytes: int = 64 << 30,
                  max_batch_tokens: int = 131072, n_streams: int = 2, max_queue: int = 4096,
-                 max_request_tokens: int = 0):
-        cfg = ServerConfigC(hbm_budget_bytes, max_batch_tokens, n_streams, max_queue, max_request_tokens)
+                 max_request_tokens: int = 0, graph_buckets: int = 0):
+        cfg = ServerConfigC(hbm_budget_bytes, max_batch_tokens, n_streams, max_queue, max_request_tokens,
+                            graph_buckets)
         h = vp()
         _check("anon_server_start", lib().anon_server_start(model.handle, cache.handle, C.byref(cfg), C.byref(h)))
         self.handle = h.value
@@ -597,11 +610,12 @@ class Server:
 
     def stats(self) -> dict:
         """anon_server_stats: arena size, peak arena bytes in use, micro-batches
-        launched, most micro-batches in flight at once."""
+        launched, most micro-batches in flight at once, forward graph replays."""
         c = ServerCountersC()
         _check("anon_server_stats", lib().anon_server_stats(self.handle, C.byref(c)))
         return {"arena_bytes": c.arena_bytes, "peak_arena_bytes": c.peak_arena_bytes,
-                "micro_batches": c.micro_batches, "max_concurrent": c.max_concurrent}
+                "micro_batches": c.micro_batches, "max_concurrent": c.max_concurrent,
+                "graph_launches": c.graph_launches}
 
     def stop(self):
         if getattr(self, "handle", None):

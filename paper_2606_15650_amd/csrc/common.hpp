@@ -50,6 +50,13 @@ void set_thread_error_word(uint32_t* w);
 
 constexpr int kWave = 64;
 
+// Rows a launch computes: its capacity `cap` (the grid is sized for it), or,
+// when `dev` is given, the count held in device memory clamped to [0, cap].
+// A graph captured for a token bucket reads the batch's count this way.
+__device__ __forceinline__ int live_rows(int cap, const int* dev) {
+  return dev ? max(0, min(*dev, cap)) : cap;
+}
+
 __device__ __forceinline__ float bf16_to_float(bf16_t x) { return static_cast<float>(x); }
 __device__ __forceinline__ bf16_t float_to_bf16(float x) { return static_cast<bf16_t>(x); }
 

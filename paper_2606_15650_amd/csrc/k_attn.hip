@@ -564,13 +564,16 @@ constexpr int kBQ = 32 * kWaves;
 // One workgroup: validates cu_seqlens and lists (first token, length, first
 // query row, record) items of bq query rows for the records whose length
 // lies in [lo, hi].
-__global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
+__global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ cu, int B, int T_cap, int max_len,
                                                         int lo, int hi, int bq, int4* __restrict__ qblocks,
-                                                        int max_q, int* __restrict__ n_qblocks, uint32_t* err) {
+                                                        int max_q, int* __restrict__ n_qblocks, uint32_t* err,
+                                                        const int* t_dev) {
   // Malformed (overlapping) cu_seqlens could ask for more items than the
   // buffer holds; writes stop at max_q and the error bit is raised.
   __shared__ int sums[1024];
   const int tid = threadIdx.x;
+  const int T = live_rows(T_cap, t_dev);
+  if (tid == 0 && t_dev && *t_dev != T) raise_error(err, ANON_ERR_SEQLENS);
   const int per = (B + 1023) / 1024;
   const int s0 = min(B, tid * per), s1 = min(B, s0 + per);
   int cnt = 0;
@@ -611,12 +614,15 @@ __global__ __launch_bounds__(1024) void seq_plan_kernel(const int* __restrict__ 
 
 // One workgroup: the BF16 kernel's work list, longest records first (in
 // bins of 32 keys), each record split into items of bq query rows.
-__global__ __launch_bounds__(1024) void stream_plan_kernel(const int* __restrict__ cu, int B, int T, int max_len,
-                                                           int bq, int4* __restrict__ items, int max_items,
-                                                           int* __restrict__ n_items, uint32_t* err) {
+__global__ __launch_bounds__(1024) void stream_plan_kernel(const int* __restrict__ cu, int B, int T_cap,
+                                                           int max_len, int bq, int4* __restrict__ items,
+                                                           int max_items, int* __restrict__ n_items, uint32_t* err,
+                                                           const int* t_dev) {
   __shared__ int sums[1024];
   __shared__ int run;
   const int tid = threadIdx.x;
+  const int T = live_rows(T_cap, t_dev);
+  if (tid == 0 && t_dev && *t_dev != T) raise_error(err, ANON_ERR_SEQLENS);
   const int per = (B + 1023) / 1024;
   const int s0 = min(B, tid * per), s1 = min(B, s0 + per);
   bool bad = false;
@@ -704,14 +710,14 @@ int attn_plan_items(ElemType t, int config, int T, int B) {
 }
 
 void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int config, int4* items,
-                      int max_items, int* n_items, uint32_t* err, hipStream_t s) {
+                      int max_items, int* n_items, uint32_t* err, hipStream_t s, const int* t_dev) {
   if (streamed(t)) {
     const int bq = 32 * kAttnCfg[cfg_index(config)].w;
     hipLaunchKernelGGL(stream_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, bq, items,
-                       max_items, n_items, err);
+                       max_items, n_items, err, t_dev);
   } else {
     hipLaunchKernelGGL(seq_plan_kernel, dim3(1), dim3(1024), 0, s, cu_seqlens, B, T, max_len, 0, max_len, kBQ,
-                       items, max_items, n_items, err);
+                       items, max_items, n_items, err, t_dev);
   }
 }
 

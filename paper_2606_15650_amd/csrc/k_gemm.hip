@@ -121,6 +121,7 @@ struct DevParams {
   const int* pos;     // EPI_ROPE: position of each row within its record
   const float* rope;  // EPI_ROPE: [max_pos][64] cos (first 32) and sin (last 32)
   int rope_cols;      // EPI_ROPE: columns below this are rotated
+  const int* m_dev;   // non-null: rows to compute (device), M is the grid's capacity
 };
 
 // The MFMAs take the weight fragment as their first operand, so each
@@ -192,7 +193,7 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
                                          int wrow0, int wcol0) {
   typedef Staging<TO, EPI, TM, TN, NW, SMEM> SG;
   constexpr int ROWB = SG::ROWB, CPR = SG::CPR, SWZ = SG::SWZ, NS = SG::NS;
-  const int M = p.M, N = p.N;
+  const int M = live_rows(p.M, p.m_dev), N = p.N;
   constexpr bool PAIRED = EPI == EPI_ROPE || EPI == EPI_GEGLU;
   static_assert(!PAIRED || TN % 2 == 0, "paired epilogues need whole 64-column blocks per wave");
   static_assert(EPI != EPI_GEGLU || sizeof(TO) >= 2, "the gated epilogue writes bf16 or fp32");
@@ -343,9 +344,14 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_kernel(DevParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  const int M = p.M, N = p.N, K = p.K;
+  const int N = p.N, K = p.K;
+  // the tiles of the rows to compute; with a device row count the grid may
+  // hold more workgroups, which leave at once, and the live tiles are spread
+  // over the XCDs as in a launch of exactly their number
+  const int M = live_rows(p.M, p.m_dev);
   const int ntn = N / BN;
   const int ntm = (M + BM - 1) / BM;
+  if ((int)blockIdx.x >= ntm * ntn) return;
   int mb, nb;
   group_tile(xcd_remap(blockIdx.x, ntm * ntn), ntm, ntn, p.group_m, mb, nb);
   const int m0 = mb * BM, n0 = nb * BN;
@@ -502,9 +508,14 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
-  const int M = p.M, N = p.N, K = p.K;
+  const int N = p.N, K = p.K;
+  // the tiles of the rows to compute; with a device row count the grid may
+  // hold more workgroups, which leave at once, and the live tiles are spread
+  // over the XCDs as in a launch of exactly their number
+  const int M = live_rows(p.M, p.m_dev);
   const int ntn = N / BN;
   const int ntm = (M + BM - 1) / BM;
+  if ((int)blockIdx.x >= ntm * ntn) return;
   int mb, nb;
   group_tile(xcd_remap(blockIdx.x, ntm * ntn), ntm, ntn, p.group_m, mb, nb);
   const int m0 = mb * BM, n0 = nb * BN;
@@ -721,7 +732,7 @@ bool run(const GemmParams& g, hipStream_t s) {
   // the XCD's L2 once per row block), else plain row-major order
   const int gm = g.group_m > 0 ? g.group_m : (g.N / BN >= 8 ? 8 : 1);
   DevParams p{g.A, g.W, g.bias, g.resid, g.C, g.M, g.N, g.K, g.qscale, g.qcols, g.acc_scale, g.out_inv_scale, gm,
-              g.ldc > 0 ? g.ldc : (g.epi == EPI_GEGLU ? g.N / 2 : g.N), g.pos, g.rope, g.rope_cols};
+              g.ldc > 0 ? g.ldc : (g.epi == EPI_GEGLU ? g.N / 2 : g.N), g.pos, g.rope, g.rope_cols, g.m_dev};
   const int tiles = ((g.M + BM - 1) / BM) * (g.N / BN);
   if constexpr (ST == 0) {
     hipLaunchKernelGGL((gemm_kernel<TI, TO, TR, EPI, BM, BN, BK, WGM, WGN, OCC>), dim3(tiles),

@@ -124,14 +124,15 @@ __device__ __forceinline__ void ln_store(float (&v)[NPL], const float (&gv)[NPL]
 
 template <int NPL>
 __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ ids, const int* __restrict__ cu,
-                                                       int B, int T, const float* __restrict__ tok,
+                                                       int B, int T_cap, const float* __restrict__ tok,
                                                        const float* __restrict__ pos, const float* __restrict__ g,
                                                        const float* __restrict__ b, float eps, int vocab,
                                                        int max_pos, void* out, ElemType out_t, fp8_t* out_q,
-                                                       float q_inv_scale, int* pos_out, uint32_t* err) {
+                                                       float q_inv_scale, int* pos_out, uint32_t* err,
+                                                       const int* t_dev) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= T) return;
+  if (t >= live_rows(T_cap, t_dev)) return;
   constexpr int h = NPL * 64;
   int id = ids[t];
   if (id < 0 || id >= vocab) {
@@ -159,9 +160,11 @@ __global__ __launch_bounds__(256) void embed_ln_kernel(const int* __restrict__ i
 // reduction, so more bytes are in flight per wave.
 template <typename TY, int NPL, int RPW>
 __global__ __launch_bounds__(256) void layernorm_kernel(const TY* __restrict__ y, const float* __restrict__ g,
-                                                        const float* __restrict__ b, float eps, int rows, void* out,
-                                                        ElemType out_t, fp8_t* out_q, float q_inv_scale) {
+                                                        const float* __restrict__ b, float eps, int rows_cap,
+                                                        void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale,
+                                                        const int* rows_dev) {
   const int lane = threadIdx.x & 63;
+  const int rows = live_rows(rows_cap, rows_dev);
   const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
   if (row0 >= rows) return;
   constexpr int h = NPL * 64;
@@ -190,10 +193,12 @@ constexpr int kMaxLabels = 64;
 // top-2 with one exchange (ties to the lowest class index).
 template <typename TX, int H>
 __global__ __launch_bounds__(256) void classifier_mfma_kernel(const TX* __restrict__ x, const float* __restrict__ wc,
-                                                              const float* __restrict__ bc, int T, int C,
+                                                              const float* __restrict__ bc, int T_cap, int C,
                                                               uint8_t* __restrict__ labels,
-                                                              float* __restrict__ logits, float* __restrict__ margin) {
+                                                              float* __restrict__ logits, float* __restrict__ margin,
+                                                              const int* t_dev) {
   const int lane = threadIdx.x & 63;
+  const int T = live_rows(T_cap, t_dev);
   const int t0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
   if (t0 >= T) return;
   const int hh = lane >> 5, r32 = lane & 31;
@@ -253,12 +258,12 @@ __global__ __launch_bounds__(256) void classifier_mfma_kernel(const TX* __restri
 
 template <typename TX, int NPL>
 __global__ __launch_bounds__(256) void classifier_kernel(const TX* __restrict__ x, const float* __restrict__ wc,
-                                                         const float* __restrict__ bc, int T, int C,
+                                                         const float* __restrict__ bc, int T_cap, int C,
                                                          uint8_t* __restrict__ labels, float* __restrict__ logits,
-                                                         float* __restrict__ margin) {
+                                                         float* __restrict__ margin, const int* t_dev) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= T) return;
+  if (t >= live_rows(T_cap, t_dev)) return;
   constexpr int h = NPL * 64;
   float xv[NPL];
 #pragma unroll
@@ -391,11 +396,12 @@ __global__ void fill_random_kernel(void* p, ElemType t, int64_t n, uint32_t seed
 
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
                      const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
-                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s, int* pos_out) {
+                     ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s, int* pos_out,
+                     const int* t_dev) {
   if (T <= 0) return;
   ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((embed_ln_kernel<NPL>), dim3(ceil_div(T, 4)), dim3(256), 0, s, ids,
                                              cu_seqlens, B, T, tok_emb, pos_emb, g, b, eps, vocab, max_pos, out,
-                                             out_t, out_q, q_inv_scale, pos_out, err));
+                                             out_t, out_q, q_inv_scale, pos_out, err, t_dev));
 }
 
 void launch_f32_to_bf16(const float* x, bf16_t* out, int64_t n, hipStream_t s) {
@@ -405,21 +411,24 @@ void launch_f32_to_bf16(const float* x, bf16_t* out, int64_t n, hipStream_t s) {
 }
 
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
-                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s) {
+                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s,
+                      const int* rows_dev) {
   if (rows <= 0) return;
   constexpr int RPW = ANON_LN_RPW;
   const int blocks = ceil_div(rows, 4 * RPW);
   if (y_t == ET_F32) {
     ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<float, NPL, RPW>), dim3(blocks), dim3(256), 0, s,
-                                               (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+                                               (const float*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale,
+                                               rows_dev));
   } else {
     ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((layernorm_kernel<bf16_t, NPL, RPW>), dim3(blocks), dim3(256), 0, s,
-                                               (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale));
+                                               (const bf16_t*)y, g, b, eps, rows, out, out_t, out_q, q_inv_scale,
+                                               rows_dev));
   }
 }
 
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
-                       uint8_t* labels, float* logits, float* margin, hipStream_t s) {
+                       uint8_t* labels, float* logits, float* margin, hipStream_t s, const int* t_dev) {
   if (T <= 0) return;
   if (C <= 32) {
     const int blocks = ceil_div(ceil_div(T, 32), 4);
@@ -427,10 +436,10 @@ void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const flo
   case HV:                                                                                                       \
     if (x_t == ET_F32)                                                                                           \
       hipLaunchKernelGGL((classifier_mfma_kernel<float, HV>), dim3(blocks), dim3(256), 0, s, (const float*)x,    \
-                         wc_t, bc, T, C, labels, logits, margin);                                                \
+                         wc_t, bc, T, C, labels, logits, margin, t_dev);                                         \
     else                                                                                                         \
       hipLaunchKernelGGL((classifier_mfma_kernel<bf16_t, HV>), dim3(blocks), dim3(256), 0, s, (const bf16_t*)x,  \
-                         wc_t, bc, T, C, labels, logits, margin);                                                \
+                         wc_t, bc, T, C, labels, logits, margin, t_dev);                                         \
     return;
     switch (h) {
       ANON_CLS_MFMA(128)
@@ -445,10 +454,10 @@ void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const flo
   }
   if (x_t == ET_F32) {
     ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((classifier_kernel<float, NPL>), dim3(ceil_div(T, 4)), dim3(256), 0,
-                                               s, (const float*)x, wc_t, bc, T, C, labels, logits, margin));
+                                               s, (const float*)x, wc_t, bc, T, C, labels, logits, margin, t_dev));
   } else {
     ANON_NPL_SWITCH(h / 64, hipLaunchKernelGGL((classifier_kernel<bf16_t, NPL>), dim3(ceil_div(T, 4)), dim3(256), 0,
-                                               s, (const bf16_t*)x, wc_t, bc, T, C, labels, logits, margin));
+                                               s, (const bf16_t*)x, wc_t, bc, T, C, labels, logits, margin, t_dev));
   }
 }
 

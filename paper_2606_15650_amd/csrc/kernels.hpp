@@ -31,6 +31,7 @@ struct GemmParams {
   const int* pos;     // EPI_ROPE: [M] position of each row within its record
   const float* rope;  // EPI_ROPE: [positions][64] cos (first 32), sin (last 32)
   int rope_cols;      // EPI_ROPE: columns below this are rotated
+  const int* m_dev;   // non-null: rows to compute, read on the device (M is then the grid's capacity)
 };
 // Returns false (and sets the error) if no kernel matches the shapes/types.
 bool launch_gemm(const GemmParams& p, hipStream_t s);
@@ -50,8 +51,10 @@ bool gemm_config_serves(const GemmParams& p, int config);
 int attn_num_configs();
 const char* attn_config_name(int config);
 int attn_plan_items(ElemType t, int config, int T, int B);
+// t_dev (nullable): the token total in device memory, at most T; cu_seqlens[B]
+// must equal it.
 void launch_attn_plan(const int* cu_seqlens, int B, int T, int max_len, ElemType t, int config, int4* items,
-                      int max_items, int* n_items, uint32_t* err, hipStream_t s);
+                      int max_items, int* n_items, uint32_t* err, hipStream_t s, const int* t_dev = nullptr);
 // window > 0: query i sees only keys j with |i - j| <= window
 void launch_attention(const void* qkv, void* out, const int4* items, int max_items, const int* n_items,
                       int n_heads, int hidden, ElemType t, ElemType out_t, float out_inv_scale, int config,
@@ -59,16 +62,20 @@ void launch_attention(const void* qkv, void* out, const int4* items, int max_ite
 
 // ---- row-wise kernels -----------------------------------------------------
 // pos_emb may be null (no learned positions); pos_out (nullable) receives
-// each token's position within its record
+// each token's position within its record.  The row kernels take T (rows)
+// as the capacity their grid covers; a non-null t_dev (rows_dev) holds the
+// count to compute, read on the device (see live_rows).
 void launch_embed_ln(const int* ids, const int* cu_seqlens, int B, int T, const float* tok_emb, const float* pos_emb,
                      const float* g, const float* b, float eps, int vocab, int max_pos, int h, void* out,
                      ElemType out_t, fp8_t* out_q, float q_inv_scale, uint32_t* err, hipStream_t s,
-                     int* pos_out = nullptr);
+                     int* pos_out = nullptr, const int* t_dev = nullptr);
 void launch_f32_to_bf16(const float* x, bf16_t* out, int64_t n, hipStream_t s);
 void launch_layernorm(const void* y, ElemType y_t, const float* g, const float* b, float eps, int rows, int h,
-                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s);
+                      void* out, ElemType out_t, fp8_t* out_q, float q_inv_scale, hipStream_t s,
+                      const int* rows_dev = nullptr);
 void launch_classifier(const void* x, ElemType x_t, const float* wc_t, const float* bc, int T, int h, int C,
-                       uint8_t* labels, float* logits, float* margin, hipStream_t s);
+                       uint8_t* labels, float* logits, float* margin, hipStream_t s,
+                       const int* t_dev = nullptr);
 void launch_to_f32(const void* x, ElemType t, float* out, int64_t n, hipStream_t s);
 void launch_transpose_convert(const float* src, int rows, int cols, void* dst, ElemType t, float inv_scale,
                               hipStream_t s);

@@ -177,7 +177,7 @@ extern "C" {
 
 const char* anon_last_error(void) { return t_last_error.c_str(); }
 
-int32_t anon_version(void) { return 3; }
+int32_t anon_version(void) { return 4; }
 
 anon_status anon_device_errors(int32_t device, uint32_t* flags, int32_t clear) {
   if (!flags) return set_error(ANON_EINVAL, "flags is NULL");
@@ -373,23 +373,26 @@ static anon_status check_batch(const anon_model* m, const void* d_ids, const voi
 static double gemm_flops(double M, double N, double K) { return 2.0 * M * N * K; }
 
 // Runs the embedding and the first n_layers layers; returns the hidden state.
+// t_dev (nullable): the token count in device memory, at most T (the
+// capacity every grid is sized for).
 static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int B, int T, int n_layers, EncWs& w,
-                               hipStream_t s) {
+                               hipStream_t s, const int* t_dev = nullptr) {
   const anon_model_config& c = m->cfg;
   const int h = c.hidden, f = c.ffn;
   uint32_t* err = error_word_ptr();
   const bool fp8 = m->gemm_t == ET_FP8;
-  launch_attn_plan(cu, B, T, c.max_pos, m->qkv_t, m->attn_cfg, w.qblocks, w.max_q, w.nq, err, s);
+  launch_attn_plan(cu, B, T, c.max_pos, m->qkv_t, m->attn_cfg, w.qblocks, w.max_q, w.nq, err, s, t_dev);
   {
     ProfScope ps(KC_EMBED, s, 0.0);
     launch_embed_ln(ids, cu, B, T, m->tok_emb, m->pos_emb, m->emb_g, m->emb_b, c.ln_eps, c.vocab, c.max_pos, h, w.x,
-                    m->act_t, w.xq, fp8 ? 1.f / m->layers[0].sa[0] : 1.f, err, s);
+                    m->act_t, w.xq, fp8 ? 1.f / m->layers[0].sa[0] : 1.f, err, s, nullptr, t_dev);
   }
   // attention FLOPs are counted from token-weighted lengths by the caller
   for (int l = 0; l < n_layers; ++l) {
     const LayerW& L = m->layers[l];
     GemmParams g{};
     g.M = T;
+    g.m_dev = t_dev;
     g.in = m->gemm_t;
     g.acc_scale = 1.f;
     g.out_inv_scale = 1.f;
@@ -439,7 +442,8 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     }
     {
       ProfScope ps(KC_LN, s, 0.0);
-      launch_layernorm(w.y, m->act_t, L.ln1_g, L.ln1_b, c.ln_eps, T, h, w.x2, m->act_t, w.xq, fp8 ? 1.f / L.sa[2] : 1.f, s);
+      launch_layernorm(w.y, m->act_t, L.ln1_g, L.ln1_b, c.ln_eps, T, h, w.x2, m->act_t, w.xq, fp8 ? 1.f / L.sa[2] : 1.f, s,
+                       t_dev);
     }
     // FFN1 + bias + GELU
     g.A = fp8 ? (const void*)w.xq : w.x2;
@@ -481,7 +485,8 @@ static anon_status run_encoder(anon_model* m, const int* ids, const int* cu, int
     {
       ProfScope ps(KC_LN, s, 0.0);
       const float nxt = (fp8 && l + 1 < c.n_layers) ? 1.f / m->layers[l + 1].sa[0] : 1.f;
-      launch_layernorm(w.y, m->act_t, L.ln2_g, L.ln2_b, c.ln_eps, T, h, w.x, m->act_t, fp8 ? w.xq : nullptr, nxt, s);
+      launch_layernorm(w.y, m->act_t, L.ln2_g, L.ln2_b, c.ln_eps, T, h, w.x, m->act_t, fp8 ? w.xq : nullptr, nxt, s,
+                       t_dev);
     }
   }
   ANON_HIP_CHECK(hipGetLastError());
@@ -503,29 +508,41 @@ anon_status anon_ner_workspace_size(const anon_model* m, int32_t T, int32_t B, s
   return ANON_OK;
 }
 
-anon_status ner_forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B, int32_t T,
-                        uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace, size_t ws_bytes,
-                        void* stream) {
-  clear_error();
+}  // extern "C"
+
+// The forward for B records and T tokens; with t_dev, B and T are capacities
+// and the kernels compute the *t_dev tokens that cu_seqlens lays out.
+static anon_status forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B, int32_t T,
+                           const int32_t* t_dev, uint8_t* d_labels, float* d_logits, float* d_margin,
+                           void* d_workspace, size_t ws_bytes, hipStream_t s) {
   anon_status st = check_batch(m, d_ids, d_cu_seqlens, B, T);
   if (st != ANON_OK) return st;
   if (T == 0) return ANON_OK;
   if (!d_labels) return set_error(ANON_EINVAL, "labels is NULL");
   if (!d_workspace || ws_bytes < enc_ws_bytes(m, T, B)) return set_error(ANON_ECAPACITY, "workspace too small");
   ANON_HIP_CHECK(hipSetDevice(m->device));
-  hipStream_t s = (hipStream_t)stream;
   Carver k(d_workspace, ws_bytes);
   EncWs w;
   enc_layout(m, T, B, k, w);
-  st = run_encoder(m, d_ids, d_cu_seqlens, B, T, m->cfg.n_layers, w, s);
+  st = run_encoder(m, d_ids, d_cu_seqlens, B, T, m->cfg.n_layers, w, s, t_dev);
   if (st != ANON_OK) return st;
   {
     ProfScope ps(KC_CLS, s, gemm_flops(T, m->cfg.n_labels, m->cfg.hidden));
     launch_classifier(w.x, m->act_t, m->wc_t, m->bc, T, m->cfg.hidden, m->cfg.n_labels, d_labels, d_logits,
-                      d_margin, s);
+                      d_margin, s, t_dev);
   }
   ANON_HIP_CHECK(hipGetLastError());
   return ANON_OK;
+}
+
+extern "C" {
+
+anon_status ner_forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B, int32_t T,
+                        uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace, size_t ws_bytes,
+                        void* stream) {
+  clear_error();
+  return forward(m, d_ids, d_cu_seqlens, B, T, nullptr, d_labels, d_logits, d_margin, d_workspace, ws_bytes,
+                 (hipStream_t)stream);
 }
 
 // The layer stack as one HIP graph: ner_forward recorded on a private
@@ -539,10 +556,12 @@ struct anon_graph {
   hipGraphExec_t exec;
 };
 
-anon_status ner_forward_capture(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
-                                int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
-                                size_t ws_bytes, anon_graph** out) {
-  clear_error();
+}  // extern "C"
+
+// Records the forward on a private stream and instantiates it.
+static anon_status capture_forward(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                                   int32_t T, const int32_t* t_dev, uint8_t* d_labels, float* d_logits,
+                                   float* d_margin, void* d_workspace, size_t ws_bytes, anon_graph** out) {
   if (!out) return set_error(ANON_EINVAL, "out is NULL");
   *out = nullptr;
   anon_status st = check_batch(m, d_ids, d_cu_seqlens, B, T);
@@ -561,7 +580,7 @@ anon_status ner_forward_capture(anon_model* m, const int32_t* d_ids, const int32
     (void)hipStreamDestroy(cs);
     return set_error(ANON_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  st = ner_forward(m, d_ids, d_cu_seqlens, B, T, d_labels, d_logits, d_margin, d_workspace, ws_bytes, cs);
+  st = forward(m, d_ids, d_cu_seqlens, B, T, t_dev, d_labels, d_logits, d_margin, d_workspace, ws_bytes, cs);
   const std::string fwd_err = anon_last_error();
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(cs, &g);
@@ -579,6 +598,27 @@ anon_status ner_forward_capture(anon_model* m, const int32_t* d_ids, const int32
   }
   *out = new anon_graph{m->device, g, x};
   return ANON_OK;
+}
+
+extern "C" {
+
+anon_status ner_forward_capture(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens, int32_t B,
+                                int32_t T, uint8_t* d_labels, float* d_logits, float* d_margin, void* d_workspace,
+                                size_t ws_bytes, anon_graph** out) {
+  clear_error();
+  return capture_forward(m, d_ids, d_cu_seqlens, B, T, nullptr, d_labels, d_logits, d_margin, d_workspace,
+                         ws_bytes, out);
+}
+
+anon_status ner_forward_capture_bucket(anon_model* m, const int32_t* d_ids, const int32_t* d_cu_seqlens,
+                                       const int32_t* d_n_tokens, int32_t B_cap, int32_t T_cap, uint8_t* d_labels,
+                                       float* d_logits, float* d_margin, void* d_workspace, size_t ws_bytes,
+                                       anon_graph** out) {
+  clear_error();
+  if (!d_n_tokens) return set_error(ANON_EINVAL, "n_tokens is NULL");
+  if (B_cap < 1 || T_cap < 1) return set_error(ANON_EINVAL, "bucket capacities must be positive");
+  return capture_forward(m, d_ids, d_cu_seqlens, B_cap, T_cap, d_n_tokens, d_labels, d_logits, d_margin,
+                         d_workspace, ws_bytes, out);
 }
 
 anon_status anon_graph_launch(anon_graph* g, void* stream) {

@@ -14,8 +14,20 @@
 // and split per request.  The thread only queries events.  Every kernel
 // computes each record independently of its batch-mates, so a request's
 // result is the same alone or mixed with others.
+//
+// With graph buckets on, each slot also owns fixed forward buffers (ids,
+// boundaries, token count, labels, error word, NER workspace) sized for the
+// largest micro-batch, and one instantiated HIP graph of the NER forward per
+// token bucket (max_batch_tokens, half of it, a quarter, ...), captured on
+// those buffers at start.  A micro-batch is uploaded into the slot's
+// buffers (its boundaries padded with empty records to the bucket) and runs
+// the forward as one graph launch of the smallest bucket that holds it; the
+// kernels read its token count from device memory.  Decoding and
+// substitution follow on the same stream as before.  The fixed buffers are
+// taken from the HBM budget before the arena.
 #include <string.h>
 
+#include <atomic>
 #include <chrono>
 #include <thread>
 #include <vector>
@@ -48,6 +60,28 @@ struct HipExecutor {
   anon_pcache* cache = nullptr;
   int n_types = 1;
   char* arena = nullptr;  // device
+  bool graphs = false;    // NER forward as bucket graph replays
+  std::vector<int> buckets;  // token capacities, largest first
+  std::atomic<int64_t> graph_launches{0};
+
+  // a slot's fixed forward buffers (graph mode), for T tokens at most
+  struct GraphBufs {
+    int32_t *ids, *cu, *n_tok;
+    uint8_t* labels;
+    uint32_t* err;
+    void* ws;
+    size_t ws_b;
+  };
+  void plan_fixed(Carver& k, int T, GraphBufs& g) const {
+    g.ids = k.take<int32_t>(T);
+    g.cu = k.take<int32_t>((size_t)T + 1);
+    g.n_tok = k.take<int32_t>(1);
+    g.labels = k.take<uint8_t>(T);
+    g.err = k.take<uint32_t>(64);
+    g.ws_b = 0;
+    anon_ner_workspace_size(model, T, T, &g.ws_b);
+    g.ws = k.take<uint8_t>(g.ws_b);
+  }
 
   struct SlotRes {
     hipStream_t stream = nullptr;
@@ -56,9 +90,11 @@ struct HipExecutor {
     int B = 0, T = 0, span_cap = 0;
     int64_t nbytes = 0, out_cap = 0;
     BatchBufs d{};
+    GraphBufs g{};
+    std::vector<anon_graph*> graph;  // per bucket
     // pinned host staging, sized for the largest micro-batch
     void* hmem = nullptr;
-    int32_t *h_ids, *h_cu, *h_tok_off, *h_cu_spans;
+    int32_t *h_ids, *h_cu, *h_tok_off, *h_cu_spans, *h_ntok;
     uint8_t *h_text, *h_labels, *h_out;
     int64_t *h_cu_bytes, *h_cu_out;
     anon_span* h_spans;
@@ -70,24 +106,26 @@ struct HipExecutor {
   // "[" + type (<= 32) + "_" + slug (<= 64) + "]" per span, besides the text
   static int64_t out_cap_for(int T, int64_t nb) { return nb + (int64_t)T * 99; }
 
+  // A micro-batch's arena block.  In graph mode its ids, boundaries,
+  // labels, error word and NER workspace are the slot's fixed buffers.
   void plan(Carver& k, int B, int T, int64_t nb, BatchBufs& b) const {
     const int sc = span_cap_for(T);
-    b.ids = k.take<int32_t>(T);
-    b.cu = k.take<int32_t>(B + 1);
+    b.ids = graphs ? nullptr : k.take<int32_t>(T);
+    b.cu = graphs ? nullptr : k.take<int32_t>(B + 1);
     b.tok_off = k.take<int32_t>(2 * (size_t)T);
     b.text = k.take<uint8_t>(nb);
     b.cu_bytes = k.take<int64_t>(B + 1);
-    b.labels = k.take<uint8_t>(T);
+    b.labels = graphs ? nullptr : k.take<uint8_t>(T);
     b.spans = k.take<anon_span>(sc);
     b.cu_spans = k.take<int32_t>(B + 1);
     b.out = k.take<uint8_t>(out_cap_for(T, nb));
     b.cu_out = k.take<int64_t>(B + 1);
-    b.err = k.take<uint32_t>(64);
+    b.err = graphs ? nullptr : k.take<uint32_t>(64);
     b.ws_ner_b = b.ws_dec_b = b.ws_ps_b = 0;
-    anon_ner_workspace_size(model, T, B, &b.ws_ner_b);
+    if (!graphs) anon_ner_workspace_size(model, T, B, &b.ws_ner_b);
     anon_decode_workspace_size(T, B, &b.ws_dec_b);
     anon_pseudonymize_workspace_size(B, sc, &b.ws_ps_b);
-    b.ws_ner = k.take<uint8_t>(b.ws_ner_b);
+    b.ws_ner = graphs ? nullptr : k.take<uint8_t>(b.ws_ner_b);
     b.ws_dec = k.take<uint8_t>(b.ws_dec_b);
     b.ws_ps = k.take<uint8_t>(b.ws_ps_b);
   }
@@ -111,6 +149,14 @@ struct HipExecutor {
     s.h_out = h.take<uint8_t>(out_cap_for(T, nb));
     s.h_cu_out = h.take<int64_t>(B + 1);
     s.h_err = h.take<uint32_t>(64);
+    s.h_ntok = h.take<int32_t>(1);
+  }
+
+  // smallest bucket that holds T tokens (buckets run largest first)
+  int bucket_for(int T) const {
+    int b = 0;
+    while (b + 1 < (int)buckets.size() && buckets[b + 1] >= T) ++b;
+    return b;
   }
 
   anon_status enqueue(int i, std::vector<Request*>& reqs, int64_t off) {
@@ -142,28 +188,48 @@ struct HipExecutor {
     if (!k.ok()) return set_error(ANON_EINVAL, "micro-batch carve exceeds its arena block");
     const BatchBufs& d = s.d;
     hipStream_t st = s.stream;
-    ANON_HIP_CHECK(hipMemcpyAsync(d.ids, s.h_ids, (size_t)T * 4, hipMemcpyHostToDevice, st));
-    ANON_HIP_CHECK(hipMemcpyAsync(d.cu, s.h_cu, (size_t)(B + 1) * 4, hipMemcpyHostToDevice, st));
+    // graph mode: the forward's inputs and outputs are the slot's fixed buffers
+    int32_t* ids = graphs ? s.g.ids : d.ids;
+    int32_t* cu = graphs ? s.g.cu : d.cu;
+    uint8_t* labels = graphs ? s.g.labels : d.labels;
+    uint32_t* err = graphs ? s.g.err : d.err;
+    const int bk = graphs ? bucket_for(T) : 0;
+    int n_cu = B + 1;
+    if (graphs) {  // empty records up to the bucket's record capacity
+      n_cu = buckets[bk] + 1;
+      for (int b = B + 1; b < n_cu; ++b) s.h_cu[b] = T;
+      *s.h_ntok = T;
+      ANON_HIP_CHECK(hipMemcpyAsync(s.g.n_tok, s.h_ntok, 4, hipMemcpyHostToDevice, st));
+    }
+    ANON_HIP_CHECK(hipMemcpyAsync(ids, s.h_ids, (size_t)T * 4, hipMemcpyHostToDevice, st));
+    ANON_HIP_CHECK(hipMemcpyAsync(cu, s.h_cu, (size_t)n_cu * 4, hipMemcpyHostToDevice, st));
     ANON_HIP_CHECK(hipMemcpyAsync(d.tok_off, s.h_tok_off, (size_t)T * 8, hipMemcpyHostToDevice, st));
     if (nb > 0) ANON_HIP_CHECK(hipMemcpyAsync(d.text, s.h_text, nb, hipMemcpyHostToDevice, st));
     ANON_HIP_CHECK(hipMemcpyAsync(d.cu_bytes, s.h_cu_bytes, (size_t)(B + 1) * 8, hipMemcpyHostToDevice, st));
-    launch_fill_u8((uint8_t*)d.err, 0, 4, st);
+    launch_fill_u8((uint8_t*)err, 0, 4, st);
     ANON_HIP_CHECK(hipGetLastError());
-    // this micro-batch's device-data errors go to its own word
-    set_thread_error_word(d.err);
-    anon_status rc = ner_forward(model, d.ids, d.cu, B, T, d.labels, nullptr, nullptr, d.ws_ner, d.ws_ner_b, st);
+    // this micro-batch's device-data errors go to its own word (graph mode:
+    // the slot's, which the slot's graphs were captured with)
+    set_thread_error_word(err);
+    anon_status rc;
+    if (graphs) {
+      rc = anon_graph_launch(s.graph[bk], st);
+      if (rc == ANON_OK) ++graph_launches;
+    } else {
+      rc = ner_forward(model, ids, cu, B, T, labels, nullptr, nullptr, d.ws_ner, d.ws_ner_b, st);
+    }
     if (rc == ANON_OK)
-      rc = decode_spans(d.labels, d.tok_off, d.cu, B, T, n_types, d.spans, s.span_cap, d.cu_spans, d.ws_dec,
+      rc = decode_spans(labels, d.tok_off, cu, B, T, n_types, d.spans, s.span_cap, d.cu_spans, d.ws_dec,
                         d.ws_dec_b, st);
     if (rc == ANON_OK)
       rc = pseudonymize(cache, d.text, d.cu_bytes, B, d.spans, d.cu_spans, s.span_cap, d.out, s.out_cap, d.cu_out,
                         d.ws_ps, d.ws_ps_b, st);
     set_thread_error_word(nullptr);
     if (rc != ANON_OK) return rc;
-    ANON_HIP_CHECK(hipMemcpyAsync(s.h_labels, d.labels, (size_t)T, hipMemcpyDeviceToHost, st));
+    ANON_HIP_CHECK(hipMemcpyAsync(s.h_labels, labels, (size_t)T, hipMemcpyDeviceToHost, st));
     ANON_HIP_CHECK(hipMemcpyAsync(s.h_cu_spans, d.cu_spans, (size_t)(B + 1) * 4, hipMemcpyDeviceToHost, st));
     ANON_HIP_CHECK(hipMemcpyAsync(s.h_cu_out, d.cu_out, (size_t)(B + 1) * 8, hipMemcpyDeviceToHost, st));
-    ANON_HIP_CHECK(hipMemcpyAsync(s.h_err, d.err, 4, hipMemcpyDeviceToHost, st));
+    ANON_HIP_CHECK(hipMemcpyAsync(s.h_err, err, 4, hipMemcpyDeviceToHost, st));
     ANON_HIP_CHECK(hipEventRecord(s.ev[0], st));
     s.phase = 0;
     return ANON_OK;
@@ -232,18 +298,21 @@ struct anon_server {
   int vocab = 0, max_pos = 0;
   int64_t max_bytes = 0;
   void* arena_mem = nullptr;
+  void* fixed_mem = nullptr;  // the slots' forward buffers (graph mode)
   std::thread th;
 };
 
 static void free_server(anon_server* sv) {
   sv->sch.reset();
   for (auto& s : sv->ex.slots) {
+    for (anon_graph* g : s.graph) anon_graph_free(g);
     for (auto& e : s.ev)
       if (e) (void)hipEventDestroy(e);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.hmem) (void)hipHostFree(s.hmem);
   }
   if (sv->arena_mem) (void)hipFree(sv->arena_mem);
+  if (sv->fixed_mem) (void)hipFree(sv->fixed_mem);
   delete sv;
 }
 
@@ -255,7 +324,7 @@ anon_status anon_server_start(anon_model* model, anon_pcache* cache, const anon_
   if (!out || !model || !cache || !cfg) return set_error(ANON_EINVAL, "NULL argument");
   *out = nullptr;
   if (cfg->max_batch_tokens < 1 || cfg->n_streams < 1 || cfg->n_streams > 8 || cfg->max_queue < 1 ||
-      cfg->hbm_budget_bytes <= 0)
+      cfg->hbm_budget_bytes <= 0 || cfg->graph_buckets < 0 || cfg->graph_buckets > 16)
     return set_error(ANON_EINVAL, "bad server config");
   anon_server* sv = new anon_server();
   sv->cfg = *cfg;
@@ -278,19 +347,36 @@ anon_status anon_server_start(anon_model* model, anon_pcache* cache, const anon_
   lim.max_queue = cfg->max_queue;
   // the arena: the budget, but no more than all slots can fill at once; it
   // must hold the largest request that submit accepts
+  // graph buckets: max_batch_tokens, then halving, at least 1 token each
+  ex.graphs = cfg->graph_buckets > 0;
+  for (int b = 0, cap = T; b < cfg->graph_buckets && cap >= 1; ++b, cap /= 2) ex.buckets.push_back(cap);
+  int64_t fixed_slot = 0;
+  if (ex.graphs) {
+    Carver fk(nullptr, SIZE_MAX);
+    HipExecutor::GraphBufs g;
+    ex.plan_fixed(fk, T, g);
+    fixed_slot = (int64_t)align_up(fk.used, 256);
+  }
+  const int64_t fixed = fixed_slot * cfg->n_streams;
   const int Rq = sv->cfg.max_request_tokens;
   const int64_t fp_slot = ex.footprint(T, T, sv->max_bytes);
   const int64_t fp_req = ex.footprint(Rq, Rq, (int64_t)Rq * 64);
-  const int64_t arena = std::min<int64_t>(cfg->hbm_budget_bytes, fp_slot * cfg->n_streams) / 256 * 256;
+  const int64_t arena =
+      std::max<int64_t>(0, std::min<int64_t>(cfg->hbm_budget_bytes - fixed, fp_slot * cfg->n_streams)) / 256 * 256;
   if (arena < anon::sched::Arena::granule(fp_req)) {
-    delete sv;
+    free_server(sv);
     return set_error(ANON_ENOMEM, "the largest admissible request needs " + std::to_string(fp_req) +
-                                      " device bytes, over the HBM budget of " +
+                                      " device bytes besides " + std::to_string(fixed) +
+                                      " bytes of slot buffers, over the HBM budget of " +
                                       std::to_string(cfg->hbm_budget_bytes));
   }
   if (hipMalloc(&sv->arena_mem, arena) != hipSuccess) {
-    delete sv;
+    free_server(sv);
     return set_error(ANON_ENOMEM, "cannot allocate the " + std::to_string(arena) + "-byte activation arena");
+  }
+  if (fixed > 0 && hipMalloc(&sv->fixed_mem, fixed) != hipSuccess) {
+    free_server(sv);
+    return set_error(ANON_ENOMEM, "cannot allocate " + std::to_string(fixed) + " bytes of slot buffers");
   }
   ex.arena = (char*)sv->arena_mem;
   ex.slots.resize(cfg->n_streams);
@@ -307,6 +393,26 @@ anon_status anon_server_start(anon_model* model, anon_pcache* cache, const anon_
     }
     Carver h(s.hmem, hbytes);
     HipExecutor::carve_host(s, h, T, T, sv->max_bytes);
+  }
+  // one forward graph per bucket and slot, captured on the slot's buffers
+  // with the slot's error word (the model's tile choices are fixed now)
+  for (int i = 0; ex.graphs && i < cfg->n_streams; ++i) {
+    HipExecutor::SlotRes& s = ex.slots[i];
+    Carver fk((char*)sv->fixed_mem + fixed_slot * i, (size_t)fixed_slot);
+    ex.plan_fixed(fk, T, s.g);
+    for (int cap : ex.buckets) {
+      anon_graph* g = nullptr;
+      set_thread_error_word(s.g.err);
+      const anon_status rc = ner_forward_capture_bucket(model, s.g.ids, s.g.cu, s.g.n_tok, cap, cap, s.g.labels,
+                                                        nullptr, nullptr, s.g.ws, s.g.ws_b, &g);
+      set_thread_error_word(nullptr);
+      if (rc != ANON_OK) {
+        const std::string why = anon_last_error();
+        free_server(sv);
+        return set_error(rc, "capturing the forward of the " + std::to_string(cap) + "-token bucket: " + why);
+      }
+      s.graph.push_back(g);
+    }
   }
   sv->sch.reset(new anon::sched::Scheduler<HipExecutor>(ex, cfg->n_streams, lim, arena));
   sv->th = std::thread([sv] {
@@ -374,6 +480,7 @@ anon_status anon_server_stats(anon_server* sv, anon_server_counters* out) {
   int conc = 0;
   sv->sch->stats(&out->peak_arena_bytes, &out->micro_batches, &conc);
   out->max_concurrent = conc;
+  out->graph_launches = sv->ex.graph_launches.load();
   return ANON_OK;
 }
 

@@ -122,3 +122,91 @@ def test_capture_errors():
     want = _eager(m, ids, cu, 2, 12)
     assert np.array_equal(lab.cpu().numpy(), want[0])
     g.close()
+
+
+def _bucket_replays_match_eager(m, T_cap, batches, seed):
+    """One graph captured for a token bucket of T_cap tokens and T_cap records;
+    batches of other sizes are written into its buffers (boundaries padded
+    with empty records, the count in device memory) and replayed twice each,
+    with eager work of the same batch between the replays.  Every replay
+    equals ner_forward on that batch alone, bit for bit, and leaves the rows
+    past the batch untouched."""
+    import torch
+    from paper_2606_15650_amd import api
+    L = m.cfg.n_labels
+    ids = torch.zeros(T_cap, dtype=torch.int32, device="cuda")
+    cu = torch.zeros(T_cap + 1, dtype=torch.int32, device="cuda")
+    n_tok = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lab, z, mg = _outputs(T_cap, L)
+    ws_bytes = m.workspace_size(T_cap, T_cap)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    g = api.ner_forward_capture_bucket(m, ids, cu, n_tok, T_cap, T_cap, lab, z, mg, ws, ws_bytes)
+    torch.cuda.synchronize()
+    for i, lengths in enumerate(batches):
+        B, T = len(lengths), int(np.sum(lengths))
+        assert B <= T_cap and T <= T_cap
+        say(f"[graph] bucket {T_cap}: batch {i}, {B} records, {T} tokens")
+        b_ids, b_cu = _lengths_batch(lengths, m.cfg.vocab, seed + i)
+        for rep in range(2):
+            want = _eager(m, b_ids, b_cu, B, T)
+            lab.fill_(255)
+            z.fill_(float("nan"))
+            mg.fill_(float("nan"))
+            ids[:T].copy_(b_ids)
+            cu[:B + 1].copy_(b_cu)
+            cu[B + 1:].fill_(T)
+            n_tok.fill_(T)
+            g.launch()
+            torch.cuda.synchronize()
+            got = (lab[:T].cpu().numpy(), z[:T].cpu().numpy(), mg[:T].cpu().numpy())
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), f"batch {i} replay {rep}"
+            assert (lab[T:].cpu().numpy() == 255).all(), "rows past the batch were written"
+    assert api.device_errors(0, clear=True) == 0
+    # a count past the bucket raises the sequence-length bit; nothing faults
+    # (records of 64 tokens that fill the bucket: only the count is wrong)
+    cu.copy_(torch.clamp(torch.arange(T_cap + 1, dtype=torch.int32, device="cuda") * 64, max=T_cap))
+    n_tok.fill_(T_cap + 5)
+    g.launch()
+    torch.cuda.synchronize()
+    assert api.device_errors(0, clear=True) & api.ERR_SEQLENS
+    g.close()
+
+
+def test_tiny_fp32_bucket_graph_replays():
+    _, m = make_model(TINY, "fp32", 0)
+    rng = np.random.default_rng(3)
+    batches = [[1], [3, 17, 1], rng.integers(16, 129, 40), np.full(32, 128)]
+    _bucket_replays_match_eager(m, 4096, batches, 30)
+
+
+def test_bf16_base_width_bucket_graph_replays():
+    """Base widths (two layers), a 16384-token bucket: batches from one token
+    to the full bucket, lengths at the attention tile edges."""
+    _, m = make_model(BASE2, "bf16", 1)
+    rng = np.random.default_rng(4)
+    ragged = np.clip(np.round(rng.lognormal(5.2, 0.6, 40)), 1, 512).astype(np.int64)
+    ragged[:4] = [1, 128, 129, 512]
+    batches = [[1], ragged, [512] * 32, [7, 300, 64]]
+    _bucket_replays_match_eager(m, 16384, batches, 40)
+
+
+def test_bucket_capture_errors():
+    import torch
+    from paper_2606_15650_amd import api
+    _, m = make_model(TINY, "fp32", 0)
+    ids = torch.zeros(64, dtype=torch.int32, device="cuda")
+    cu = torch.zeros(65, dtype=torch.int32, device="cuda")
+    n_tok = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lab, z, mg = _outputs(64, TINY.n_labels)
+    ws_bytes = m.workspace_size(64, 64)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(api.AnonError) as e:
+        api.ner_forward_capture_bucket(m, ids, cu, None, 64, 64, lab, z, mg, ws, ws_bytes)
+    assert e.value.status == -1  # EINVAL: no count
+    with pytest.raises(api.AnonError) as e:
+        api.ner_forward_capture_bucket(m, ids, cu, n_tok, 0, 64, lab, z, mg, ws, ws_bytes)
+    assert e.value.status == -1  # EINVAL: empty bucket
+    with pytest.raises(api.AnonError) as e:
+        api.ner_forward_capture_bucket(m, ids, cu, n_tok, 64, 64, lab, z, mg, ws, ws_bytes - 1)
+    assert e.value.status == -4  # ECAPACITY

@@ -184,3 +184,63 @@ def test_budget_too_small_fails_at_start():
     say("[server] start with a budget below one slot")
     with pytest.raises(api.AnonError):
         api.Server(m, cache, hbm_budget_bytes=1 << 20, max_batch_tokens=4096, n_streams=2)
+
+
+def test_graph_bucket_server_equals_eager_server_alone_and_mixed():
+    """Graph buckets on, base-width model (two layers, 17 labels): every forward
+    runs as a graph replay; each request's labels, spans and bytes are the same
+    alone, in the mix and from the eager server."""
+    from paper_2606_15650_amd import api
+    from synth.configs import ModelConfig
+    base2 = ModelConfig(n_layers=2, hidden=768, n_heads=12, ffn=3072, vocab=30522, n_labels=17)
+    W, m = make_model(base2, "bf16", 2)
+    cache = make_cache(synth.TYPE_NAMES_17[:8])
+    rb = synth.generate_records(90, ("uniform", 16, 512), 8, base2.vocab, 47)
+    reqs = _requests(rb, [1, 7, 3, 12, 20, 5, 9, 2, 15, 16])
+    eager = api.Server(m, cache, hbm_budget_bytes=8 << 30, max_batch_tokens=16384, n_streams=3, max_queue=256)
+    say("[server] eager server, requests together")
+    ref = [_wait(eager, t) for t in [_submit(eager, q) for q in reqs]]
+    eager.stop()
+    sv = api.Server(m, cache, hbm_budget_bytes=8 << 30, max_batch_tokens=16384, n_streams=3, max_queue=256,
+                    graph_buckets=6)
+    say("[server] graph buckets, requests one at a time")
+    alone = []
+    for q in reqs:
+        t = _submit(sv, q)
+        alone.append(_wait(sv, t))
+        sv.release(t)
+    say("[server] graph buckets, requests together")
+    tickets = [_submit(sv, q) for q in reqs]
+    mixed = [_wait(sv, t) for t in tickets]
+    st = sv.stats()
+    sv.stop()
+    say(f"[server] graph-bucket server stats {st}")
+    assert st["graph_launches"] == st["micro_batches"] > len(reqs)
+    for a, b, c, q in zip(alone, mixed, ref, reqs):
+        for r in (a, b, c):
+            assert r["status"] == 0
+        for r in (a, b):
+            np.testing.assert_array_equal(r["labels"], c["labels"])
+            np.testing.assert_array_equal(r["spans"], c["spans"])
+            assert r["out"] == c["out"]
+            np.testing.assert_array_equal(r["cu_out"], c["cu_out"])
+    m.close()
+    cache.close()
+
+
+def test_graph_bucket_server_start_errors():
+    from paper_2606_15650_amd import api
+    W, m = make_model(TINY, "bf16", 0)
+    cache = make_cache(synth.TYPE_NAMES_9)
+    with pytest.raises(api.AnonError):
+        api.Server(m, cache, hbm_budget_bytes=8 << 30, max_batch_tokens=4096, n_streams=2, graph_buckets=17)
+    # the fixed slot buffers count against the budget: one that holds the
+    # eager server's arena does not hold them as well
+    eager = api.Server(m, cache, hbm_budget_bytes=8 << 30, max_batch_tokens=4096, n_streams=2, max_queue=8)
+    need = eager.stats()["arena_bytes"]
+    eager.stop()
+    with pytest.raises(api.AnonError):
+        api.Server(m, cache, hbm_budget_bytes=need // 2 + (need // 2) // 4, max_batch_tokens=4096, n_streams=2,
+                   graph_buckets=4)
+    m.close()
+    cache.close()

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_library_loads_and_binding_matches_header():
     from paper_2606_15650_amd import api
     L = api.lib()
-    assert L.anon_version() == 3
+    assert L.anon_version() == 4
     assert sorted(api.EXPORTED) == declared_functions()
     # argument checks need no GPU
     import ctypes as C

@@ -79,3 +79,42 @@ def windows(cu_seqlens, window: int, stride: int):
         for s in window_starts(n, window, stride):
             rows.append((r, s, min(window, n - s)))
     return np.asarray(rows, dtype=np.int64).reshape(-1, 3)
+
+
+def confident_spans(spans, margin, tok_off, cu_seqlens, threshold: float = 1e-2, exclude=()) -> list:
+    """The spans (rows record, type, begin, end) whose tokens, and the token just
+    before and just after them within their record, all have ``margin`` above
+    ``threshold``; tokens listed in ``exclude`` (global indices) count as not
+    confident.  Such a span is decided by confident labels only: BIO decoding
+    of a span depends on the labels of its own tokens and its two neighbours.
+    (Evaluation helper of the parity gates, not part of the method.)"""
+    cu = np.asarray(cu_seqlens, dtype=np.int64)
+    ok = np.asarray(margin) > threshold
+    if len(exclude):
+        ok = ok.copy()
+        ok[np.asarray(list(exclude), dtype=np.int64)] = False
+    tok_off = np.asarray(tok_off)
+    out = []
+    for r, t, b, e in np.asarray(spans, dtype=np.int64).reshape(-1, 4).tolist():
+        a0, a1 = int(cu[r]), int(cu[r + 1])
+        inside = np.nonzero((tok_off[a0:a1, 0] >= b) & (tok_off[a0:a1, 1] <= e))[0]
+        if len(inside) == 0:
+            continue
+        lo, hi = max(a0 + int(inside[0]) - 1, a0), min(a0 + int(inside[-1]) + 1, a1 - 1)
+        if ok[lo:hi + 1].all():
+            out.append((r, t, b, e))
+    return out
+
+
+def confident_span_gate(labels_a, labels_ref, margin_ref, tok_off, cu_seqlens, n_types: int,
+                        threshold: float = 1e-2, exclude=()) -> dict:
+    """Span gate between labels ``labels_a`` and reference labels: every
+    confident reference span (by the reference margins) must be among a's
+    spans, and every confident span of a among the reference's.  Counts."""
+    sa = bio_decode(labels_a, tok_off, cu_seqlens, n_types)
+    sr = bio_decode(labels_ref, tok_off, cu_seqlens, n_types)
+    ca = confident_spans(sa, margin_ref, tok_off, cu_seqlens, threshold, exclude)
+    cr = confident_spans(sr, margin_ref, tok_off, cu_seqlens, threshold, exclude)
+    set_a, set_r = set(map(tuple, sa.tolist())), set(map(tuple, sr.tolist()))
+    return {"confident_ref_spans": len(cr), "missing_in_a": [s for s in cr if s not in set_a],
+            "confident_a_spans": len(ca), "missing_in_ref": [s for s in ca if s not in set_r]}

@@ -114,7 +114,7 @@ def confident_records(margin_ref: np.ndarray, cu: np.ndarray) -> list[int]:
     return [b for b in range(len(cu) - 1) if (margin_ref[cu[b]:cu[b + 1]] > MARGIN).all()]
 
 
-def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
+def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS, batch=None, n_types=None) -> int:
     """Reduced-precision labels against the rounding oracle (zq, lq, mq).
 
     Every token whose oracle margin exceeds 1e-2 must carry the oracle's
@@ -125,7 +125,11 @@ def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
     below the seed's own largest logit deviation from the oracle.  The number
     of accepted tokens is printed, and may not exceed three times (at least
     two) the number of labels above 1e-2 that the perturbed oracle itself
-    flips.  Returns that number."""
+    flips.  With ``batch`` (its tok_off and cu_seqlens) and ``n_types``, the
+    span gate follows: every span whose tokens and two neighbours are all
+    confident (accepted tokens count as not confident) is the same in the GPU's
+    and the oracle's decoding, in both directions.  Returns the number of
+    accepted tokens."""
     from oracle import sensitivity
     conf = mq > MARGIN
     bad = np.nonzero(conf & (lab != lq))[0]
@@ -140,4 +144,10 @@ def reduced_label_gate(lab, zq, lq, mq, perturbed, seeds=PERTURB_SEEDS) -> int:
         f"{len(accepted)} accepted as ambiguous (perturbed oracle flips {own_flips})")
     assert not rejected, f"labels differ above margin 1e-2 at tokens {rejected[:20]} (margins {mq[rejected[:20]]})"
     assert len(accepted) <= max(2, 3 * own_flips), (len(accepted), own_flips)
+    if batch is not None:
+        from oracle import spans
+        g = spans.confident_span_gate(lab, lq, mq, batch.tok_off, batch.cu_seqlens, n_types, MARGIN, accepted)
+        say(f"  span gate: {g['confident_ref_spans']} confident oracle spans, {len(g['missing_in_a'])} missing on "
+            f"the GPU; {g['confident_a_spans']} confident GPU spans, {len(g['missing_in_ref'])} not the oracle's")
+        assert not g["missing_in_a"] and not g["missing_in_ref"], g
     return len(accepted)

@@ -96,7 +96,7 @@ def test_bf16_against_the_rounding_oracle_alone_and_packed(torch_dev):
     say(f"[modern bf16] max |z - z_bf16oracle| {err:.3e} (perturbed spread {spread:.3e}); "
         f"vs pure {np.abs(z - zp).max():.3e}")
     assert err < max(2 * spread, 1e-3)
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd])
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd], batch=rb, n_types=MODERN_TINY.n_types)
     for r in (0, 1, 3, 6):
         a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
         l1, z1, _ = _ner(m, rb.subset([r]))
@@ -154,5 +154,5 @@ def test_modernbert_base_sampled_records(torch_dev):
     err = np.abs(z - zq).max()
     say(f"  max |z - z_bf16oracle| {err:.3e} (perturbed spread {spread:.3e}), O-rate {(lq == 0).mean():.3f}")
     assert err < 2 * spread
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd])
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd], batch=rb, n_types=MODERN_BASE.n_types)
     m.close()

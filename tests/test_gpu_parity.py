@@ -422,7 +422,8 @@ def test_base_bf16_small_batch_vs_rounding_oracle(torch_dev):
     bound = LOGIT_BOUND[("bf16", BASE.n_layers)]
     say(f"  max |z-zq| {dev_q:.3e}  max |z-zpure| {dev_p:.3e}  O-rate {(lab == 0).mean():.3f}")
     assert dev_q < bound and dev_p < bound
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, BASE, rb, "bf16", sd))
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, BASE, rb, "bf16", sd), batch=rb,
+                       n_types=BASE.n_types)
     m.close()
 
 
@@ -475,7 +476,8 @@ def test_base_bf16_full_batch_sampled_records(torch_dev):
     dev = np.abs(z_full[rows] - zq).max()
     say(f"  max |z - z_bf16oracle| {dev:.3e} (bound {LOGIT_BOUND[('bf16', BASE.n_layers)]})")
     assert dev < LOGIT_BOUND[("bf16", BASE.n_layers)]
-    reduced_label_gate(lab[rows], zq, lq, mq, lambda sd: _perturbed(W, BASE, sub, "bf16", sd))
+    reduced_label_gate(lab[rows], zq, lq, mq, lambda sd: _perturbed(W, BASE, sub, "bf16", sd), batch=sub,
+                       n_types=BASE.n_types)
     key = synth.make_key(0)
     res = opipe.run(W, BASE, sub, key, 10, labels_override=lab[rows])
     for i, r in enumerate(sample):
@@ -627,7 +629,8 @@ def test_large_fp8_records_at_every_attention_class_bound(torch_dev):
         a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
         say(f"  record {r} ({n} tokens): max |z - z_oracle| {np.abs(z[a:b] - zq[a:b]).max():.3e}")
     assert np.abs(z - zq).max() < bound
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, LARGE, rb, "fp8", sd, sc))
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: _perturbed(W, LARGE, rb, "fp8", sd, sc), batch=rb,
+                       n_types=LARGE.n_types)
     for r in range(len(FP8_CLASS_LENGTHS)):
         a, b = int(rb.cu_seqlens[r]), int(rb.cu_seqlens[r + 1])
         l1, z1, _ = _run_ner(m, rb.subset([r]))
@@ -659,7 +662,7 @@ def test_fp8_attention_length_classes_two_layers(torch_dev):
     spread = max(np.abs(r[0] - zq).max() for r in runs.values())
     say(f"  max |z - z_fp8oracle| {err:.3e}; perturbed oracle spread {spread:.3e}")
     assert err < 2 * spread
-    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd])
+    reduced_label_gate(lab, zq, lq, mq, lambda sd: runs[sd], batch=rb, n_types=4)
     for r in range(len(lens)):
         a, b = rb.cu_seqlens[r], rb.cu_seqlens[r + 1]
         l1, z1, _ = _run_ner(m, rb.subset([r]))

@@ -135,3 +135,50 @@ def test_output_length_identity_and_unchanged_bytes():
 def test_substitute_rejects_overlapping_spans():
     with pytest.raises(ValueError):
         pseudonym.substitute(b"abcdef", [(1, 0, 3), (1, 2, 4)], ["T"], b"k", 4)
+
+
+def test_confident_spans_hand_made():
+    # one record of 8 tokens, two types: spans at tokens 1-2 (type 1), 4 (type 2), 7 (type 1)
+    lab = np.array([0, 1, 2, 0, 3, 0, 0, 1])
+    off = np.array([[3 * i, 3 * i + 2] for i in range(8)])
+    cu = np.array([0, 8])
+    sp = spans.bio_decode(lab, off, cu, 2)
+    assert sp.tolist() == [[0, 1, 3, 8], [0, 2, 12, 14], [0, 1, 21, 23]]
+    margin = np.ones(8)
+    margin[5] = 1e-3  # the token after the second span
+    got = spans.confident_spans(sp, margin, off, cu)
+    # the last span has no token after it inside the record
+    assert got == [(0, 1, 3, 8), (0, 1, 21, 23)]
+    assert spans.confident_spans(sp, margin, off, cu, exclude=[0]) == [(0, 1, 21, 23)]
+
+
+def test_confident_span_gate_only_sees_confident_disagreements():
+    """Brute force over random label pairs: labels that differ only on
+    unconfident tokens never fail the gate; a difference on a confident token
+    inside or next to a confident span does."""
+    rng = np.random.default_rng(5)
+    n_types = 3
+    caught = 0
+    for trial in range(300):
+        lens = rng.integers(1, 12, 4)
+        cu = np.concatenate([[0], np.cumsum(lens)])
+        T = int(cu[-1])
+        off = np.zeros((T, 2), dtype=np.int64)
+        for r in range(4):
+            k = np.arange(lens[r])
+            off[cu[r]:cu[r + 1], 0], off[cu[r]:cu[r + 1], 1] = 3 * k, 3 * k + 2
+        ref = rng.integers(0, 2 * n_types + 1, T)
+        margin = np.where(rng.random(T) < 0.3, 1e-3, 1.0)
+        other = ref.copy()
+        soft = np.nonzero(margin <= 1e-2)[0]
+        other[soft] = rng.integers(0, 2 * n_types + 1, len(soft))
+        g = spans.confident_span_gate(other, ref, margin, off, cu, n_types)
+        assert not g["missing_in_a"] and not g["missing_in_ref"], trial
+        # change one confident token
+        hard = np.nonzero(margin > 1e-2)[0]
+        if len(hard):
+            t = int(rng.choice(hard))
+            other[t] = (ref[t] + 1 + rng.integers(0, 2 * n_types)) % (2 * n_types + 1)
+            g = spans.confident_span_gate(other, ref, margin, off, cu, n_types)
+            caught += bool(g["missing_in_a"] or g["missing_in_ref"])
+    assert caught > 100

@@ -172,9 +172,13 @@ void anon_graph_free(anon_graph* graph);
 /* GEMM tile autotuner.  Times every tile configuration that fits each of the
  * four encoder GEMMs (0 QKV, 1 output projection, 2 FFN1, 3 FFN2) on T rows,
  * using d_workspace (>= anon_ner_workspace_size(T, 1) bytes; overwritten) as
- * operand memory, and keeps the fastest for this model's later calls.  All
- * configurations of a precision form every output element with the same
- * MFMA sequence in the same K order, so tuning never changes results.
+ * operand memory, and keeps the fastest for this model's later calls; then,
+ * with that tile, it times the tile orders (groups of 2, 4, 6, 8 or 12 row
+ * blocks against the order by shape, see anon_model_set_tile_groups) and
+ * keeps one that is at least 1% faster than the order by shape.  All
+ * configurations and orders of a precision form every output element with
+ * the same MFMA sequence in the same K order, so tuning never changes
+ * results.
  *   chosen:   [4] picked configuration per GEMM, or NULL
  *   times_ms: [4 * max_configs] mean time per configuration (-1: does not
  *             fit the shape), or NULL

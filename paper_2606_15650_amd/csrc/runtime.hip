@@ -756,6 +756,34 @@ anon_status anon_autotune(anon_model* m, int32_t T, void* d_workspace, size_t ws
     }
     m->gemm_cfg[gi] = best_c;
     if (chosen) chosen[gi] = best_c;
+    // then the tile order of that tile: groups of 2..12 row blocks against
+    // the order by shape (kept unless another is at least 1% faster)
+    if (st != ANON_OK) break;
+    g.config = best_c;
+    const int kGroups[] = {0, 2, 4, 6, 8, 12};
+    constexpr int NG = (int)(sizeof(kGroups) / sizeof(int));
+    float gbest[NG];
+    for (int j = 0; j < NG; ++j) gbest[j] = 1e30f;
+    for (int round = 0; round < 2 && st == ANON_OK; ++round) {
+      for (int j = 0; j < NG; ++j) {
+        g.group_m = kGroups[j];
+        const int reps = 5;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) launch_gemm(g, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          st = set_error(ANON_EDEVICE, "autotune: kernel failed");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        gbest[j] = std::min(gbest[j], ms / reps);
+      }
+    }
+    int gsel = 0;
+    for (int j = 1; j < NG; ++j)
+      if (gbest[j] < gbest[gsel] * (gsel == 0 ? 0.99f : 1.0f)) gsel = j;
+    m->gemm_gm[gi] = kGroups[gsel];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

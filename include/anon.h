@@ -112,6 +112,26 @@ anon_status anon_model_create(const anon_model_config* cfg, const float* h_weigh
                               anon_model** out);
 void anon_model_free(anon_model* model);
 
+/* Versioned weights file.  Layout (little-endian): a 64-byte header --
+ * "ANONWTS1", uint32 format version (1), uint32 kind (0: this BERT-style
+ * encoder), anon_model_config (32 bytes), uint64 float count, uint64
+ * FNV-1a-64 hash of the float bytes -- then the FP32 weights in
+ * anon_model_create's order.
+ *   anon_weights_write: writes `h_weights` (n_floats, checked against the
+ *     config) to `path`; ANON_EINVAL if the file cannot be written.
+ *   anon_weights_info: reads and checks a file (magic, version, kind,
+ *     config, float count, file size, hash) without touching a device; the
+ *     config and float count are returned through the non-NULL pointers.
+ *   anon_model_load: anon_weights_info's checks, then anon_model_create with
+ *     the file's config and weights.
+ * A malformed, truncated or corrupt file is ANON_EINVAL (the message says
+ * which check failed); the file is only read during the call. */
+anon_status anon_weights_write(const char* path, const anon_model_config* cfg, const float* h_weights,
+                               size_t n_floats);
+anon_status anon_weights_info(const char* path, anon_model_config* cfg, size_t* n_floats);
+anon_status anon_model_load(const char* path, anon_precision precision, const float* h_act_scales, int32_t device,
+                            anon_model** out);
+
 /* Device workspace bytes that ner_forward needs for a batch of T tokens in
  * B records (an upper bound, valid for any batch with at most T tokens and B
  * records). */

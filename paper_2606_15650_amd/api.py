@@ -80,6 +80,9 @@ _SIGS = {
     "anon_device_errors": ([i32, C.POINTER(C.c_uint32), i32], i32),
     "anon_model_create": ([C.POINTER(ModelConfigC), vp, sz, i32, vp, i32, C.POINTER(vp)], i32),
     "anon_model_free": ([vp], None),
+    "anon_weights_write": ([C.c_char_p, C.POINTER(ModelConfigC), vp, sz], i32),
+    "anon_weights_info": ([C.c_char_p, C.POINTER(ModelConfigC), C.POINTER(sz)], i32),
+    "anon_model_load": ([C.c_char_p, i32, vp, i32, C.POINTER(vp)], i32),
     "anon_ner_workspace_size": ([vp, i32, i32, C.POINTER(sz)], i32),
     "ner_forward": ([vp, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp], i32),
     "anon_encoder_hidden": ([vp, vp, vp, i32, i32, i32, vp, vp, sz, vp], i32),
@@ -176,24 +179,59 @@ def stream_handle(stream=None) -> int | None:
 
 
 # ------------------------------------------------------------------ model --
-class Model:
-    """An encoder uploaded to one device (``anon_model_create``)."""
+def _config_c(cfg) -> ModelConfigC:
+    return ModelConfigC(cfg.n_layers, cfg.hidden, cfg.n_heads, cfg.ffn, cfg.vocab, cfg.n_labels, cfg.max_pos,
+                        cfg.ln_eps)
 
-    def __init__(self, cfg, weights_blob: np.ndarray, precision: str = "bf16", act_scales=None, device: int = 0):
-        blob = np.ascontiguousarray(weights_blob, dtype=np.float32)
+
+def write_weights(path: str, cfg, weights_blob: np.ndarray):
+    """anon_weights_write: the versioned weights file of an encoder."""
+    blob = np.ascontiguousarray(weights_blob, dtype=np.float32)
+    c = _config_c(cfg)
+    _check("anon_weights_write", lib().anon_weights_write(os.fsencode(path), C.byref(c), blob.ctypes.data,
+                                                          blob.size))
+
+
+def weights_info(path: str) -> tuple[dict, int]:
+    """anon_weights_info: (config fields, float count) of a checked weights file."""
+    c, n = ModelConfigC(), sz()
+    _check("anon_weights_info", lib().anon_weights_info(os.fsencode(path), C.byref(c), C.byref(n)))
+    return {f: getattr(c, f) for f, _ in ModelConfigC._fields_}, n.value
+
+
+class Model:
+    """An encoder uploaded to one device (``anon_model_create``; ``Model.load``
+    for ``anon_model_load`` of a weights file)."""
+
+    def __init__(self, cfg, weights_blob: np.ndarray | None, precision: str = "bf16", act_scales=None,
+                 device: int = 0, path: str | None = None):
         self.cfg = cfg
         self.precision = precision
-        c = ModelConfigC(cfg.n_layers, cfg.hidden, cfg.n_heads, cfg.ffn, cfg.vocab, cfg.n_labels, cfg.max_pos,
-                         cfg.ln_eps)
         sc = None
         if act_scales is not None:
             self._scales = np.ascontiguousarray(np.asarray(act_scales, dtype=np.float32).reshape(-1))
             sc = self._scales.ctypes.data
         h = vp()
-        _check("anon_model_create", lib().anon_model_create(C.byref(c), blob.ctypes.data, blob.size,
-                                                            PRECISION[precision], sc, device, C.byref(h)))
+        if path is not None:
+            _check("anon_model_load", lib().anon_model_load(os.fsencode(path), PRECISION[precision], sc, device,
+                                                            C.byref(h)))
+        else:
+            blob = np.ascontiguousarray(weights_blob, dtype=np.float32)
+            c = _config_c(cfg)
+            _check("anon_model_create", lib().anon_model_create(C.byref(c), blob.ctypes.data, blob.size,
+                                                                PRECISION[precision], sc, device, C.byref(h)))
         self.handle = h.value
         self.device = device
+
+    @classmethod
+    def load(cls, path: str, cfg, precision: str = "bf16", act_scales=None, device: int = 0) -> "Model":
+        """The encoder of a weights file; ``cfg`` (the caller's description of
+        it) must match the file's config."""
+        got, _ = weights_info(path)
+        want = {f: getattr(_config_c(cfg), f) for f, _ in ModelConfigC._fields_}
+        if got != want:
+            raise AnonError("anon_model_load", -1, f"weights file config {got} differs from {want}")
+        return cls(cfg, None, precision, act_scales, device, path=path)
 
     def workspace_size(self, T: int, B: int) -> int:
         n = sz()

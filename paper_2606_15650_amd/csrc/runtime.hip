@@ -2,6 +2,8 @@
 // workspace carving, the encoder driver, span decoding, pseudonym caches,
 // kernel timing, and the C ABI entry points of include/anon.h.
 #include <math.h>
+#include <stddef.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -329,6 +331,129 @@ void anon_model_free(anon_model* m) {
   hipSetDevice(m->device);
   hipFree(m->mem);
   delete m;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ weights file --
+// A 64-byte header -- "ANONWTS1", format version, kind (0: the BERT-style
+// encoder), the model config, the float count, the FNV-1a-64 hash of the
+// float bytes -- then the FP32 weights in anon_model_create's order, all
+// little-endian.
+namespace {
+struct WeightsHeader {
+  char magic[8];
+  uint32_t version, kind;
+  anon_model_config cfg;
+  uint64_t n_floats, fnv;
+};
+static_assert(sizeof(WeightsHeader) == 64 && offsetof(WeightsHeader, cfg) == 16 &&
+                  offsetof(WeightsHeader, n_floats) == 48,
+              "weights header layout");
+constexpr char kWeightsMagic[8] = {'A', 'N', 'O', 'N', 'W', 'T', 'S', '1'};
+constexpr uint32_t kWeightsVersion = 1;
+
+uint64_t fnv1a64(const void* data, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+  const uint8_t* p = (const uint8_t*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 0x100000001b3ull;
+  return h;
+}
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+
+// Reads and checks the header and, if `w` is given, the weights (hash
+// included); touches no device.
+anon_status read_weights(const char* path, WeightsHeader& h, std::vector<float>* w) {
+  if (!path) return set_error(ANON_EINVAL, "path is NULL");
+  File f;
+  f.f = fopen(path, "rb");
+  if (!f.f) return set_error(ANON_EINVAL, std::string("cannot open ") + path);
+  if (fread(&h, sizeof h, 1, f.f) != 1) return set_error(ANON_EINVAL, "weights file shorter than its header");
+  if (memcmp(h.magic, kWeightsMagic, 8) != 0) return set_error(ANON_EINVAL, "not a weights file (magic)");
+  if (h.version != kWeightsVersion)
+    return set_error(ANON_EINVAL, "weights file version " + std::to_string(h.version) + ", this library reads " +
+                                      std::to_string(kWeightsVersion));
+  if (h.kind != 0) return set_error(ANON_EINVAL, "weights file holds another encoder kind");
+  anon_status st = check_cfg(&h.cfg);
+  if (st != ANON_OK) return st;
+  if (h.n_floats != n_weight_floats(h.cfg))
+    return set_error(ANON_EINVAL, "weights file holds " + std::to_string(h.n_floats) + " floats, its config needs " +
+                                      std::to_string(n_weight_floats(h.cfg)));
+  if (fseek(f.f, 0, SEEK_END) != 0) return set_error(ANON_EINVAL, "cannot size the weights file");
+  const long size = ftell(f.f);
+  if (size < 0 || (uint64_t)size != sizeof h + h.n_floats * sizeof(float))
+    return set_error(ANON_EINVAL, "weights file size does not match its header");
+  if (!w) return ANON_OK;
+  if (fseek(f.f, (long)sizeof h, SEEK_SET) != 0) return set_error(ANON_EINVAL, "cannot read the weights");
+  try {
+    w->resize(h.n_floats);
+  } catch (...) {
+    return set_error(ANON_ENOMEM, "no host memory for the weights");
+  }
+  if (fread(w->data(), sizeof(float), h.n_floats, f.f) != h.n_floats)
+    return set_error(ANON_EINVAL, "cannot read the weights");
+  if (fnv1a64(w->data(), h.n_floats * sizeof(float)) != h.fnv)
+    return set_error(ANON_EINVAL, "weights file hash mismatch (corrupt file)");
+  return ANON_OK;
+}
+}  // namespace
+
+extern "C" {
+
+anon_status anon_weights_write(const char* path, const anon_model_config* cfg, const float* h_weights,
+                               size_t n_floats) {
+  clear_error();
+  if (!path || !h_weights) return set_error(ANON_EINVAL, "NULL argument");
+  anon_status st = check_cfg(cfg);
+  if (st != ANON_OK) return st;
+  if (n_floats != n_weight_floats(*cfg))
+    return set_error(ANON_EINVAL, "weights hold " + std::to_string(n_floats) + " floats, the config needs " +
+                                      std::to_string(n_weight_floats(*cfg)));
+  WeightsHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, kWeightsMagic, 8);
+  h.version = kWeightsVersion;
+  h.kind = 0;
+  h.cfg = *cfg;
+  h.n_floats = n_floats;
+  h.fnv = fnv1a64(h_weights, n_floats * sizeof(float));
+  File f;
+  f.f = fopen(path, "wb");
+  if (!f.f) return set_error(ANON_EINVAL, std::string("cannot create ") + path);
+  if (fwrite(&h, sizeof h, 1, f.f) != 1 || fwrite(h_weights, sizeof(float), n_floats, f.f) != n_floats)
+    return set_error(ANON_EINVAL, std::string("cannot write ") + path);
+  const int rc = fclose(f.f);
+  f.f = nullptr;
+  if (rc != 0) return set_error(ANON_EINVAL, std::string("cannot write ") + path);
+  return ANON_OK;
+}
+
+anon_status anon_weights_info(const char* path, anon_model_config* cfg, size_t* n_floats) {
+  clear_error();
+  WeightsHeader h;
+  std::vector<float> w;
+  const anon_status st = read_weights(path, h, &w);
+  if (st != ANON_OK) return st;
+  if (cfg) *cfg = h.cfg;
+  if (n_floats) *n_floats = h.n_floats;
+  return ANON_OK;
+}
+
+anon_status anon_model_load(const char* path, anon_precision precision, const float* h_act_scales, int32_t device,
+                            anon_model** out) {
+  clear_error();
+  if (!out) return set_error(ANON_EINVAL, "out is NULL");
+  *out = nullptr;
+  WeightsHeader h;
+  std::vector<float> w;
+  const anon_status st = read_weights(path, h, &w);
+  if (st != ANON_OK) return st;
+  return anon_model_create(&h.cfg, w.data(), w.size(), precision, h_act_scales, device, out);
 }
 
 }  // extern "C"

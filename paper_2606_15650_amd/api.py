@@ -151,7 +151,32 @@ def lib() -> C.CDLL:
             f.argtypes = args
             f.restype = res
         _lib = L
+        if os.environ.get("ANON_TRACE", "") not in ("", "0"):
+            _start_trace()
     return _lib
+
+
+def _start_trace():
+    """ANON_TRACE=1: time every kernel class from the first use of the library
+    on (HIP events on the launch streams) and print the totals to stderr at
+    exit.  While it is on, forward graphs cannot be captured (the capture
+    calls refuse with ANON_EINVAL)."""
+    import atexit
+    import sys
+    for k in KCLASS:
+        lib().anon_prof_enable(KCLASS[k], 1)
+
+    def report():
+        rows = []
+        for k in KCLASS:
+            r = prof_read(k)
+            if r["launches"]:
+                tf = r["flops"] / (r["ms"] * 1e-3) / 1e12 if r["flops"] and r["ms"] else None
+                rows.append(f"  {k:6s} launches {r['launches']:7d}  total {r['ms']:10.3f} ms  "
+                            f"mean {r['ms'] / r['launches']:8.4f} ms" + (f"  {tf:7.1f} TFLOP/s" if tf else ""))
+        print("[ANON_TRACE] kernel time per class\n" + "\n".join(rows), file=sys.stderr, flush=True)
+
+    atexit.register(report)
 
 
 def _check(fn: str, st: int) -> int:

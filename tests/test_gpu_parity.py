@@ -668,3 +668,46 @@ def test_fp8_attention_length_classes_two_layers(torch_dev):
         l1, z1, _ = _run_ner(m, rb.subset([r]))
         np.testing.assert_array_equal(z1, z[a:b], err_msg=f"record of {lens[r]} tokens")
     m.close()
+
+
+def test_record_permutation_and_repeated_runs_are_bit_identical(tiny_fp32, tiny_batch):
+    """The batch in another record order gives each record the same logits,
+    and running the same batch again gives the same bits."""
+    _, m = tiny_fp32
+    perm = np.random.default_rng(21).permutation(tiny_batch.n_records)
+    lab0, z0, _ = _run_ner(m, tiny_batch)
+    lab1, z1, _ = _run_ner(m, tiny_batch)
+    assert np.array_equal(z0, z1) and np.array_equal(lab0, lab1)
+    pb = tiny_batch.subset(perm.tolist())
+    _, zp, _ = _run_ner(m, pb)
+    cu, cp = tiny_batch.cu_seqlens, pb.cu_seqlens
+    for new, old in enumerate(perm):
+        np.testing.assert_array_equal(zp[cp[new]:cp[new + 1]], z0[cu[old]:cu[old + 1]])
+
+
+@pytest.mark.parametrize("case", ["decreasing", "too_long", "total"])
+def test_malformed_cu_seqlens_are_flagged_not_faulting(tiny_fp32, case):
+    """Boundaries that are not non-decreasing, a record longer than max_pos
+    (no windowing) or a last boundary short of T set the sequence-length
+    bit; the kernels clamp and skip, nothing faults, and the next call is
+    unaffected."""
+    import torch
+    from paper_2606_15650_amd import api
+    _, m = tiny_fp32
+    T = 700
+    cu = {"decreasing": [0, 300, 200, 700], "too_long": [0, 50, 50 + TINY.max_pos + 10, 700],
+          "total": [0, 100, 300, 650]}[case]
+    ids = torch.from_numpy(np.random.default_rng(3).integers(0, TINY.vocab, T, dtype=np.int32)).cuda()
+    cu_d = torch.tensor(cu, dtype=torch.int32, device="cuda")
+    lab = torch.empty(T, dtype=torch.uint8, device="cuda")
+    ws_b = m.workspace_size(T, 3)
+    ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda")
+    api.device_errors(0, clear=True)
+    say(f"[errors] cu_seqlens {cu}")
+    api.ner_forward(m, ids, cu_d, 3, T, lab, None, None, ws, ws_b)
+    torch.cuda.synchronize()
+    assert api.device_errors(0, clear=True) & api.ERR_SEQLENS
+    # the library is still usable
+    rb = synth.generate_records(4, ("uniform", 16, 64), TINY.n_types, TINY.vocab, 2)
+    _run_ner(m, rb)
+    assert api.device_errors(0, clear=True) == 0

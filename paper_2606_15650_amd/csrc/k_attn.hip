@@ -396,7 +396,8 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
 
   // The issue walk runs one tile ahead of the compute walk, also across work
   // items: while the last tile of an item is used, the first tile of the
-  // next is in flight, and the next item's Q rows are loaded right after.
+  // next is in flight, and the next item's Q rows are loaded during the
+  // last tile of the one before it.
   Walk cw, iw;
   start(cw, blockIdx.x);
   if (cw.wi >= n_work) return;
@@ -426,9 +427,24 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     if (iw.wi < n_work) issue(iw, ST ^ 1);
     const int qw = cw.q0 + wave * 32;  // this wave's first query row
     const bool active = qw < cw.L;
+    // On the item's last tile the next item's Q rows go into qf as soon as
+    // the tile's last QK products have read it, so their load runs behind
+    // this tile's softmax and P V instead of ahead of the next tile.
+    const bool last = cw.t + 1 == cw.nt;
+    Walk nw;
+    bool q_loaded = !last;
+    if (last) start(nw, cw.wi + gridDim.x);
+    auto next_q = [&]() {
+      if (!q_loaded) {
+        if (nw.wi < n_work) load_q(nw);
+        q_loaded = true;
+      }
+    };
     if (active) {
       const char* ks = smem + ST * STAGE;
       const bool last_partial = (cw.t + 1) * KT > cw.L;
+      // the last 64-key step of this tile that can run (keys left in the record)
+      const int h_last = min(KT / 64, (cw.L - cw.t * KT + 63) / 64) - 1;
 #pragma unroll
       for (int h64 = 0; h64 < KT / 64; ++h64) {
         // keys of this 64-key step still inside the record (uniform)
@@ -457,6 +473,7 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
             s[b] = MF::mma(a, qf[kk], s[b]);
           }
         }
+        if (h64 == h_last) next_q();
         if (band_edge) {
           // key k of this lane's query q is seen iff |q - k| <= window
           const int dq = qw + (lane & 31) - (k0 + hh * 4);  // q - (key of r = 0 in block 0)
@@ -529,6 +546,7 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
         }
       }
     }
+    next_q();  // (a wave without rows here, or a window that skipped the last steps)
     if (++cw.t < cw.nt) return true;
     // the item is done: normalise and store, then start the next one
     if (active) {
@@ -548,9 +566,8 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
           }
       }
     }
-    start(cw, cw.wi + gridDim.x);
+    cw = nw;
     if (cw.wi >= n_work) return false;
-    load_q(cw);
     reset();
     return true;
   };

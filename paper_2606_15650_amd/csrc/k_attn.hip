@@ -398,10 +398,13 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
   // items: while the last tile of an item is used, the first tile of the
   // next is in flight, and the next item's Q rows are loaded during the
   // last tile of the one before it.
-  Walk cw, iw;
+  // inx: the item after the issue walk's, its descriptor loaded one item
+  // ahead so that a switch of the issue walk waits for no load
+  Walk cw, iw, inx;
   start(cw, blockIdx.x);
   if (cw.wi >= n_work) return;
   iw = cw;
+  start(inx, iw.wi + gridDim.x);
   issue(iw, 0);
   load_q(cw);
   floatx16 o[2];
@@ -423,7 +426,10 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     // previous tile, whose stage takes the next one
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (++iw.t == iw.nt) start(iw, iw.wi + gridDim.x);
+    if (++iw.t == iw.nt && iw.wi < n_work) {
+      iw = inx;
+      if (iw.wi < n_work) start(inx, iw.wi + gridDim.x);
+    }
     if (iw.wi < n_work) issue(iw, ST ^ 1);
     const int qw = cw.q0 + wave * 32;  // this wave's first query row
     const bool active = qw < cw.L;
@@ -431,9 +437,9 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     // the tile's last QK products have read it, so their load runs behind
     // this tile's softmax and P V instead of ahead of the next tile.
     const bool last = cw.t + 1 == cw.nt;
-    Walk nw;
+    // the issue walk, one tile ahead, is at the next item's first tile now
+    const Walk nw = iw;
     bool q_loaded = !last;
-    if (last) start(nw, cw.wi + gridDim.x);
     auto next_q = [&]() {
       if (!q_loaded) {
         if (nw.wi < n_work) load_q(nw);

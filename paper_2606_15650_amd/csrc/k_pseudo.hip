@@ -235,9 +235,13 @@ __global__ void ps_hash_kernel(PcacheDev pc, const uint8_t* __restrict__ text, c
     uint64_t slot = fp & pc.mask;
     for (int i = 0; i < kMaxProbe; ++i, slot = (slot + 1) & pc.mask) {
       Entry* e = table + slot;
-      const uint32_t stt = __hip_atomic_load(&e->state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t stt = __hip_atomic_load(&e->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (stt == 0) break;
-      if (stt == 2 && e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) {
+      if (stt != 2) continue;
+      // a ready entry: this fence pairs with its writer's release fence, so
+      // the entry's fields read below are the ones written before "ready"
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) dg[k] = e->digest[k];
         have = true;
@@ -253,8 +257,12 @@ __global__ void ps_hash_kernel(PcacheDev pc, const uint8_t* __restrict__ text, c
       uint64_t slot = fp & pc.mask;
       for (int i = 0; i < kMaxProbe; ++i, slot = (slot + 1) & pc.mask) {
         Entry* e = table + slot;
+        // claiming an empty slot reads nothing of another writer's, so the
+        // claim needs no ordering; the fields are published by one release
+        // fence ahead of the "ready" store (a fence is a cache write-back on
+        // this part: one per wave instead of one per atomic)
         uint32_t expected = 0;
-        if (__hip_atomic_compare_exchange_strong(&e->state, &expected, 1u, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+        if (__hip_atomic_compare_exchange_strong(&e->state, &expected, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)) {
           e->len = (uint32_t)len;
           e->fp = fp;
@@ -263,13 +271,17 @@ __global__ void ps_hash_kernel(PcacheDev pc, const uint8_t* __restrict__ text, c
           for (int k = 0; k < 8; ++k) e->digest[k] = dg[k];
           e->type = sp.type;
           e->first = e->last = pc.call;
-          __hip_atomic_store(&e->state, 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_store(&e->state, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           atomicAdd(&pc.counters[2], 1ull);
           break;
         }
-        if (expected == 2 && e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) {
-          touch(e, sp.type, pc.call);
-          break;
+        if (expected == 2) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (e->fp == fp && e->len == (uint32_t)len && same_bytes(e->bytes, msg, (int)len)) {
+            touch(e, sp.type, pc.call);
+            break;
+          }
         }
       }
     }

@@ -140,3 +140,75 @@ def test_many_duplicate_inserts_of_one_entity_in_one_call(torch_dev):
     st2 = cache.stats()
     assert st2["hits"] - st["hits"] == len(spans)
     cache.close()
+
+
+def test_concurrent_calls_on_two_streams_share_one_table(torch_dev):
+    """Two calls enqueued back to back on two streams with one table (as the
+    server's slots run them; whether their kernels overlap is up to the
+    device, and the first pair's hit count shows it): the same batch on both,
+    then another batch beside a repeat of the first (misses beside hits).
+    Every output equals the oracle's, the counters add up, and the export
+    holds each distinct cached entity once."""
+    import torch
+    from paper_2606_15650_amd.pipeline import DeviceBatch, Pipeline, outputs_to_list
+    rb_a = synth.generate_records(400, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 61)
+    rb_c = synth.generate_records(300, ("lognormal", 5.2, 0.6, 16, 512), 8, 30522, 62)
+    cache = make_cache(rb_a.type_names)
+    key = synth.make_key(0)
+
+    def prep(rb):
+        sp = rb.gold_spans
+        raw = np.zeros((max(len(sp), 1), 3), np.int64)
+        raw[:len(sp), 0] = (sp[:, 0] & 0xFFFFFFFF) | (sp[:, 1] << 32)
+        raw[:len(sp), 1:] = sp[:, 2:4]
+        counts = np.bincount(sp[:, 0], minlength=rb.n_records)
+        cu = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        return DeviceBatch(rb), torch.from_numpy(raw).cuda(), torch.from_numpy(cu).cuda(), max(len(sp), 1)
+
+    def pipe():
+        pl = Pipeline.__new__(Pipeline)
+        pl.cache, pl.device, pl._ws = cache, torch.device("cuda:0"), {}
+        return pl
+
+    a, c = prep(rb_a), prep(rb_c)
+    # only entities of at most 96 bytes are looked up (longer ones are hashed every time)
+    n_a = int(((rb_a.gold_spans[:, 3] - rb_a.gold_spans[:, 2]) <= 96).sum())
+    n_c = int(((rb_c.gold_spans[:, 3] - rb_c.gold_spans[:, 2]) <= 96).sum())
+    want_a = ops.pseudonymize_batch(rb_a.text, rb_a.cu_bytes, rb_a.gold_spans, rb_a.n_records, rb_a.type_names,
+                                    key, cache.slug)
+    want_c = ops.pseudonymize_batch(rb_c.text, rb_c.cu_bytes, rb_c.gold_spans, rb_c.n_records, rb_c.type_names,
+                                    key, cache.slug)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    p1, p2 = pipe(), pipe()
+    torch.cuda.synchronize()
+    say(f"[pcache] two streams: {len(rb_a.gold_spans)} spans on each, one table")
+    o1 = p1.pseudonymize(a[0], a[1], a[2], a[3], stream=s1)
+    o2 = p2.pseudonymize(a[0], a[1], a[2], a[3], stream=s2)
+    torch.cuda.synchronize()
+    assert outputs_to_list(*o1) == want_a
+    assert outputs_to_list(*o2) == want_a
+    st = cache.stats()
+    say(f"  first pair: {st}")
+    assert st["lookups"] == 2 * n_a
+    assert st["entries"] <= st["lookups"] - st["hits"]
+    # a new batch beside a repeat of the first
+    p1, p2 = pipe(), pipe()
+    o1 = p1.pseudonymize(c[0], c[1], c[2], c[3], stream=s1)
+    o2 = p2.pseudonymize(a[0], a[1], a[2], a[3], stream=s2)
+    torch.cuda.synchronize()
+    assert outputs_to_list(*o1) == want_c
+    assert outputs_to_list(*o2) == want_a
+    st2 = cache.stats()
+    say(f"  second pair: {st2}")
+    assert st2["lookups"] == st["lookups"] + n_a + n_c
+    assert st2["hits"] - st["hits"] >= n_a  # the repeat meets only cached entities
+    # the export: each distinct entity of at most 96 bytes once
+    ents = set()
+    for rb in (rb_a, rb_c):
+        for r, _, b, e in rb.gold_spans:
+            if e - b <= 96:
+                ents.add(bytes(rb.text[rb.cu_bytes[r] + b:rb.cu_bytes[r] + e]))
+    rows = cache.export()
+    originals = [r["original"] for r in rows]
+    assert len(originals) == len(set(originals))
+    assert set(originals) == ents

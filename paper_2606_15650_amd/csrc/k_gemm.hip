@@ -209,6 +209,33 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
     for (int q = 0; q < 4; ++q) bias[j][q] = *(const floatx4*)(p.bias + wcol0 + j * 32 + q * 8 + lq);
 #pragma unroll
   for (int i0 = 0; i0 < TM; i0 += NS) {
+    if constexpr (EPI == EPI_RESID) {
+      // 0. the residual of strips [i0, i0 + NS) straight into the staging
+      // slots its outputs take (residual and output have one element size):
+      // 16-byte row-contiguous global -> LDS copies, lane l of a copy taking
+      // slot l % CPR of staged row (copy rows) + l / CPR, i.e. the chunk
+      // that the row's XOR permutation puts there.  Read per lane in the
+      // accumulator layout instead, every load would touch 32 rows for 16
+      // bytes of each.
+      static_assert(sizeof(TR) == sizeof(TO), "the residual is staged in the output's layout");
+      static_assert(ROWB <= 1024 && 1024 % ROWB == 0, "whole staged rows per copy instruction");
+      constexpr int RPC = 1024 / ROWB;  // staged rows per copy instruction
+      const int nss = min(TM - i0, NS);  // strips of this pass
+      const int crow = lane / CPR, cslot = lane % CPR;
+      // a uniform base row (rows past M re-read row M-1, which the clamped
+      // base keeps at or below every lane's row) and 32-bit lane offsets
+      const int brow = min(wrow0 + i0 * 32, M - 1);
+      const char* rbase = (const char*)p.resid + ((size_t)brow * N + wcol0) * sizeof(TR);
+#pragma unroll
+      for (int t = 0; t < NS * 32 / RPC; ++t) {
+        if (t * RPC >= nss * 32) break;
+        const int srow = t * RPC + crow;
+        const int grow = min(wrow0 + (i0 + (srow >> 5)) * 32 + (srow & 31), M - 1);
+        const uint32_t off = (uint32_t)((grow - brow) * N * (int)sizeof(TR) + (cslot ^ (srow & SWZ)) * 16);
+        dma16(rbase + off, stg + t * 1024);
+      }
+      wait_vmcnt<0>();
+    }
     // 1. outputs of strips [i0, i0 + NS) into LDS
 #pragma unroll
     for (int is = 0; is < NS && i0 + is < TM; ++is) {
@@ -274,9 +301,11 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int cl = j * 32 + q * 8 + lq;  // column within the wave's block
-          const int col = wcol0 + cl;
+          const int byte = cl * (int)sizeof(TO);
+          const int chunk = (byte >> 4) ^ (srow & SWZ);
+          char* slot = stg + srow * ROWB + chunk * 16 + (byte & 15);
           float rv[4] = {0.f, 0.f, 0.f, 0.f};
-          if constexpr (EPI == EPI_RESID) ld4((const TR*)p.resid + (size_t)grow * N + col, rv);
+          if constexpr (EPI == EPI_RESID) ld4((const TR*)slot, rv);  // staged above
           float v[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -293,9 +322,7 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
             }
             v[e] = x;
           }
-          const int byte = cl * (int)sizeof(TO);
-          const int chunk = (byte >> 4) ^ (srow & SWZ);
-          st4((TO*)(stg + srow * ROWB + chunk * 16 + (byte & 15)), v);
+          st4((TO*)slot, v);
         }
       }
     }

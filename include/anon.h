@@ -271,6 +271,8 @@ anon_status anon_modern_get_tiles(const anon_modern* model, int32_t tiles[5], in
 
 /* Attention tile autotuner: times every attention tile configuration of a
  * BF16/FP8 model (query rows per work item, keys per LDS tile, ring stages)
+ * (and, for BF16 outputs, the form of the output stores: 16-byte stores
+ * after a half-wave exchange or 8-byte stores of the accumulator quads)
  * on the given packed batch's record lengths (random Q, K, V of T rows in
  * the workspace, which must hold anon_ner_workspace_size(T, B) bytes) and
  * keeps the fastest for later calls.  Every configuration gives the same

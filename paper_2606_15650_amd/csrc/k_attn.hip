@@ -277,19 +277,23 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // ---- BF16 streaming kernel ------------------------------------------------
 // Tile configurations: W waves (32 query rows each, so 32*W rows per work
 // item), KT keys per LDS tile, WPE waves per SIMD the register budget is
-// held to.  Results do not depend on the configuration: every query row sees
-// the same keys in the same 64-key reference steps.
+// held to, SW the form of the BF16 output stores (1: 16-byte stores after a
+// half-wave exchange, 0: 8-byte stores of the accumulator quads; which is
+// faster depends on the record lengths).  Results do not depend on the
+// configuration: every query row sees the same keys in the same 64-key
+// reference steps, and both store forms write the same bytes.
 struct AttnCfg {
   int w, kt, wpe;
   const char* name;
 };
 #define ANON_ATTN_CFGS(X)                    \
-  X(0, 4, 64, 4, "attn_w4_kt64_o4")          \
-  X(1, 4, 64, 3, "attn_w4_kt64_o3")          \
-  X(2, 8, 64, 4, "attn_w8_kt64_o4")          \
-  X(3, 2, 64, 3, "attn_w2_kt64_o3")          \
-  X(4, 8, 128, 3, "attn_w8_kt128_o3")
-#define ANON_ATTN_ROW(i, w, kt, wpe, name) {w, kt, wpe, name},
+  X(0, 4, 64, 4, 1, "attn_w4_kt64_o4")       \
+  X(1, 4, 64, 3, 1, "attn_w4_kt64_o3")       \
+  X(2, 8, 64, 4, 1, "attn_w8_kt64_o4")       \
+  X(3, 2, 64, 3, 1, "attn_w2_kt64_o3")       \
+  X(4, 8, 128, 3, 1, "attn_w8_kt128_o3")     \
+  X(5, 8, 64, 4, 0, "attn_w8_kt64_o4_st8")
+#define ANON_ATTN_ROW(i, w, kt, wpe, sw, name) {w, kt, wpe, name},
 const AttnCfg kAttnCfg[] = {ANON_ATTN_CFGS(ANON_ATTN_ROW)};
 constexpr int kAttnCfgs = (int)(sizeof(kAttnCfg) / sizeof(AttnCfg));
 constexpr int kAttnDefault = 0;
@@ -310,7 +314,7 @@ struct Walk {
   int base, L, q0, head;
 };
 
-template <typename TO, int W, int KT, int WPE>
+template <typename TO, int W, int KT, int WPE, int SW>
 __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* __restrict__ qkv,
                                                                   TO* __restrict__ out,
                                                                   const int4* __restrict__ items,
@@ -555,7 +559,48 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
     next_q();  // (a wave without rows here, or a window that skipped the last steps)
     if (++cw.t < cw.nt) return true;
     // the item is done: normalise and store, then start the next one
-    if (active) {
+    if (active && SW && sizeof(TO) == 2) {
+      // BF16 output.  The two half-waves hold the same 32 rows, in quads of
+      // 4 columns that alternate between them (columns 8g + 4hh + 0..3 of
+      // quad g); exchanging quads 1 and 3 of the lower half with quads 0 and
+      // 2 of the upper half (v_permlane32_swap) leaves every lane 8
+      // consecutive columns, which go out in 16-byte stores: half the
+      // store instructions, each touching 32 rows as before.
+      const int qrow = cw.q0 + wave * 32 + (lane & 31);
+      const float inv = 1.0f / (lsum + __shfl_xor(lsum, 32, 64));
+      uint32_t w[2][4][2];
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const uint32_t lo = __builtin_bit_cast(uint16_t, static_cast<bf16_t>(o[db][g * 4 + 2 * k] * inv));
+            const uint32_t hi = __builtin_bit_cast(uint16_t, static_cast<bf16_t>(o[db][g * 4 + 2 * k + 1] * inv));
+            w[db][g][k] = lo | (hi << 16);
+          }
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int g = 0; g < 4; g += 2)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            // lower lanes keep quad g and take the upper half's quad g;
+            // upper lanes take the lower half's quad g+1 and keep theirs
+            const auto r = __builtin_amdgcn_permlane32_swap(w[db][g][k], w[db][g + 1][k], false, false);
+            w[db][g][k] = r[0];
+            w[db][g + 1][k] = r[1];
+          }
+      if (qrow < cw.L) {
+        TO* dst = out + (size_t)(cw.base + qrow) * hidden + cw.head * D;
+#pragma unroll
+        for (int db = 0; db < 2; ++db)
+#pragma unroll
+          for (int g = 0; g < 4; g += 2)
+            *(uint4*)(dst + db * 32 + g * 8 + hh * 8) =
+                uint4{w[db][g][0], w[db][g][1], w[db][g + 1][0], w[db][g + 1][1]};
+      }
+    } else if (active) {
       const int qrow = cw.q0 + wave * 32 + (lane & 31);
       const float inv = 1.0f / (lsum + __shfl_xor(lsum, 32, 64));
       if (qrow < cw.L) {
@@ -698,19 +743,19 @@ int workgroups_per_cu(const AttnCfg& c) {
   return std::max(1, std::min(by_regs, by_lds));
 }
 
-template <typename TO, int W, int KT, int WPE>
+template <typename TO, int W, int KT, int WPE, int SW>
 void launch_stream(const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads, int hidden,
                    float out_inv_scale, int window, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((attn_stream_kernel<TO, W, KT, WPE>), dim3(grid), dim3(W * 64), 0, s, qkv, out, items,
+  hipLaunchKernelGGL((attn_stream_kernel<TO, W, KT, WPE, SW>), dim3(grid), dim3(W * 64), 0, s, qkv, out, items,
                      n_items, n_heads, hidden, out_inv_scale, window);
 }
 
 template <typename TO>
 void dispatch_stream(int ci, const bf16_t* qkv, TO* out, const int4* items, const int* n_items, int n_heads,
                      int hidden, float out_inv_scale, int window, int grid, hipStream_t s) {
-#define ANON_ATTN_CASE(i, w, kt, wpe, name)                                                                    \
-  case i:                                                                                                      \
-    launch_stream<TO, w, kt, wpe>(qkv, out, items, n_items, n_heads, hidden, out_inv_scale, window, grid, s); \
+#define ANON_ATTN_CASE(i, w, kt, wpe, sw, name)                                                                    \
+  case i:                                                                                                          \
+    launch_stream<TO, w, kt, wpe, sw>(qkv, out, items, n_items, n_heads, hidden, out_inv_scale, window, grid, s); \
     return;
   switch (ci) { ANON_ATTN_CFGS(ANON_ATTN_CASE) }
 #undef ANON_ATTN_CASE

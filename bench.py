@@ -53,9 +53,12 @@ def counter_traffic(workload: str, kernel: str, tile: str | None):
         sha = hashlib.sha256(f.read()).hexdigest()
     if c.get("source_sha256") != sha:
         return None, f"{src} changed since the counters were taken"
-    if tile is not None and c.get("tile") != tile:
-        return None, f"counters taken on tile {c.get('tile')}, this run chose {tile}"
-    return float(c["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    # one entry per tile and tile order the counters were taken on
+    entries = c.get("entries", [c])
+    for e in entries:
+        if tile is None or e.get("tile") == tile:
+            return float(e["bytes_per_launch"]), f"{os.path.relpath(path, ROOT)} ({e.get('tile')})"
+    return None, f"counters taken on tiles {[e.get('tile') for e in entries]}, this run chose {tile}"
 
 
 def attention_flops(cu: np.ndarray, cfg) -> float:
@@ -566,6 +569,9 @@ def main() -> int:
     ap.add_argument("--serve-graphs", type=int, default=8,
                     help="token-bucket graphs per server slot (0: launch the forward kernel by kernel)")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy first (counter scale)")
+    ap.add_argument("--ffn1-group", type=int, default=-1,
+                    help="profiling runs: the FFN1 tile order after the autotuner (0 = by shape, N = groups of N "
+                         "row blocks; default: the autotuner's)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving run (100 req/s) of the default line")
     ap.add_argument("--no-recognizers", action="store_true",
@@ -634,6 +640,10 @@ def main() -> int:
             db = DeviceBatch(rb)
             stream = torch.cuda.current_stream()
             tiles, _ = pl.autotune(T, B)
+            if a.ffn1_group >= 0:  # a fixed FFN1 tile order (counter runs cover every order)
+                g = model.get_tiles()[1]
+                g[2] = a.ffn1_group
+                model.set_tile_groups(g)
             attn_pick, attn_times = pl.autotune_attention(db)
             kept["attn_config"] = {"chosen": model.attn_configs()[attn_pick] if attn_pick >= 0 else "fp32",
                                    "times_ms": {n: float(t) for n, t in zip(model.attn_configs(), attn_times)

@@ -54,3 +54,22 @@ def test_modern_attention_flops_count_the_window_pairs():
     n_glob = len(range(0, MODERN_BASE.n_layers, MODERN_BASE.global_every))
     assert f["attn"] == 4 * MODERN_BASE.hidden * (n_glob * full + (MODERN_BASE.n_layers - n_glob) * band)
     assert f["ffn1"] == MODERN_BASE.n_layers * 2 * 768 * 2 * 1152 * 829
+
+
+def test_traffic_is_read_for_the_tile_order_the_run_chose():
+    """The FFN1 counter file holds one entry per tile order; the bench takes
+    the entry of the order its own run chose, and none for an order the
+    counters were not taken on (or for a GEMM source that changed since)."""
+    path = os.path.join(ROOT, "profiles", "base_bf16_ffn1_counters.json")
+    with open(path) as f:
+        c = json.load(f)
+    entries = c["entries"]
+    assert len({e["tile"] for e in entries}) == len(entries) >= 2
+    for e in entries:
+        got, src = bench.counter_traffic("base_bf16", "ffn1", e["tile"])
+        if got is None:  # the kernel source changed after the counters were taken
+            assert "changed" in src
+            return
+        assert got == e["bytes_per_launch"] and e["tile"] in src
+    got, src = bench.counter_traffic("base_bf16", "ffn1", "bf16_no_such_tile")
+    assert got is None and "this run chose bf16_no_such_tile" in src

@@ -611,9 +611,9 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
   const int KT = K / BK;
-  // The ring always holds ST tiles in flight or resident; refills past the
-  // last tile re-read tile KT-1 (valid memory, never multiplied), so the loop
-  // body has no data-dependent branches and the wait counts are constants.
+  // The ring always holds ST tiles in flight or resident; with more than two
+  // stages, refills past the last tile re-read tile KT-1 (valid memory, never
+  // multiplied), so the wait counts stay constants.
 #pragma unroll
   for (int s = 0; s < ST; ++s) issue(min(s, KT - 1), s);
   wait_vmcnt<(ST - 1) * LPT>();
@@ -653,7 +653,10 @@ __global__ __launch_bounds__(WGM* WGN * 64, OCC) void gemm_dma_kernel(DevParams 
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) (vmcnt, expcnt at maxima)
         wait_vmcnt<(ST - 2) * LPT>();
         __builtin_amdgcn_s_barrier();
-        issue(min(kt + ST, KT - 1), stage);
+        // past the last tile: a two-stage ring waits for every load, so the
+        // refill is left out (nothing to land before the epilogue); deeper
+        // rings re-read tile KT-1 to keep their wait counts constant
+        if (ST > 2 || kt + ST < KT) issue(min(kt + ST, KT - 1), stage);
         const char* nbase = smem + nstage * STAGE;
 #pragma unroll
         for (int i = 0; i < TM; ++i) fa[cur ^ 1][i] = rdfrag(nbase, aoff[0], i);

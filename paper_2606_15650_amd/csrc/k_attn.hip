@@ -277,9 +277,9 @@ __global__ __launch_bounds__(WAVES * 64) void attn_kernel(const T* __restrict__ 
 // ---- BF16 streaming kernel ------------------------------------------------
 // Tile configurations: W waves (32 query rows each, so 32*W rows per work
 // item), KT keys per LDS tile, WPE waves per SIMD the register budget is
-// held to, SW the form of the BF16 output stores (1: 16-byte stores after a
-// half-wave exchange, 0: 8-byte stores of the accumulator quads; which is
-// faster depends on the record lengths).  Results do not depend on the
+// held to, SW the form of the output stores (1: 16-byte BF16 or 8-byte FP8
+// stores after a half-wave exchange, 0: stores of the accumulator quads;
+// which is faster depends on the record lengths).  Results do not depend on the
 // configuration: every query row sees the same keys in the same 64-key
 // reference steps, and both store forms write the same bytes.
 struct AttnCfg {
@@ -599,6 +599,41 @@ __global__ __launch_bounds__(W * 64, WPE) void attn_stream_kernel(const bf16_t* 
           for (int g = 0; g < 4; g += 2)
             *(uint4*)(dst + db * 32 + g * 8 + hh * 8) =
                 uint4{w[db][g][0], w[db][g][1], w[db][g + 1][0], w[db][g + 1][1]};
+      }
+    } else if (active && SW && sizeof(TO) == 1) {
+      // FP8 output: the same exchange on one dword (four E4M3 values) per
+      // quad, then 8-byte stores of 8 consecutive columns
+      const int qrow = cw.q0 + wave * 32 + (lane & 31);
+      const float inv = 1.0f / (lsum + __shfl_xor(lsum, 32, 64));
+      uint32_t w[2][4];
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t x = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            // rounded to bf16 (the stored attention output), then scaled
+            // and rounded to E4M3, as element by element below
+            const float v = static_cast<float>(static_cast<bf16_t>(o[db][g * 4 + e] * inv)) * out_inv_scale;
+            x |= (uint32_t)f32_to_e4m3(v) << (8 * e);
+          }
+          w[db][g] = x;
+        }
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int g = 0; g < 4; g += 2) {
+          const auto r = __builtin_amdgcn_permlane32_swap(w[db][g], w[db][g + 1], false, false);
+          w[db][g] = r[0];
+          w[db][g + 1] = r[1];
+        }
+      if (qrow < cw.L) {
+        TO* dst = out + (size_t)(cw.base + qrow) * hidden + cw.head * D;
+#pragma unroll
+        for (int db = 0; db < 2; ++db)
+#pragma unroll
+          for (int g = 0; g < 4; g += 2) *(uint2*)(dst + db * 32 + g * 8 + hh * 8) = uint2{w[db][g], w[db][g + 1]};
       }
     } else if (active) {
       const int qrow = cw.q0 + wave * 32 + (lane & 31);

@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_row(const bf16_t* src, int lane, float (&v)
 #pragma unroll
   for (int c = 0; c < NPL / RM::VEC; ++c) {
     if constexpr (RM::VEC == 4) {
-      const bf16x4 x = *(const bf16x4*)(src + RM::col(c * 4, lane));
+      const bf16x4 x = __builtin_nontemporal_load((const bf16x4*)(src + RM::col(c * 4, lane)));
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[c * 4 + k] = static_cast<float>(x[k]);
     } else {
@@ -108,7 +108,7 @@ __device__ __forceinline__ void ln_store(float (&v)[NPL], const float (&gv)[NPL]
 #pragma unroll
       for (int k = 0; k < RM::VEC; ++k) yb[k] = static_cast<bf16_t>(y[k]);
       if constexpr (RM::VEC == 4) {
-        *(bf16x4*)((bf16_t*)out + row * h + c0) = bf16x4{yb[0], yb[1], yb[2], yb[3]};
+        __builtin_nontemporal_store(bf16x4{yb[0], yb[1], yb[2], yb[3]}, (bf16x4*)((bf16_t*)out + row * h + c0));
       } else {
 #pragma unroll
         for (int k = 0; k < RM::VEC; ++k) ((bf16_t*)out)[row * h + c0 + k] = yb[k];

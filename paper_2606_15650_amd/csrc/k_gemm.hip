@@ -337,7 +337,9 @@ __device__ __forceinline__ void epilogue(const DevParams& p, floatx16 (&acc)[TM]
       const int i = i0 + srow / 32;  // past TM only in a last, partial pass
       const int grow = wrow0 + i * 32 + (srow & 31);
       const intx4 v = *(const intx4*)(stg + srow * ROWB + ((cc ^ (srow & SWZ)) * 16));
-      if (i < TM && grow < M) *(intx4*)((char*)p.C + ((size_t)grow * p.ldc + ocol0) * sizeof(TO) + cc * 16) = v;
+      // (single-use streams: the next kernel reads them from memory)
+      if (i < TM && grow < M)
+        __builtin_nontemporal_store(v, (intx4*)((char*)p.C + ((size_t)grow * p.ldc + ocol0) * sizeof(TO) + cc * 16));
     }
     if (i0 + NS < TM) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

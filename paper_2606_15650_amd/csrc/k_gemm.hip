@@ -130,10 +130,10 @@ struct DevParams {
 // consecutive columns of one row per register quad.
 //
 // Epilogue: once the K loop is done, the operand LDS is reused.  Each wave
-// forms its outputs -- bias, Q scaling, GELU or the residual (loaded in the
-// same layout, added in FP32, rounded once) -- and parks them in its own LDS
-// region in the output type, then writes the region back with 16-byte
-// row-contiguous stores.  Loads come before stores wherever possible: on
+// forms its outputs -- bias, Q scaling, GELU or the residual (copied first
+// into the LDS slots its outputs take, added in FP32, rounded once) -- and
+// parks them in its own LDS region in the output type, then writes the
+// region back with 16-byte row-contiguous stores.  Loads come before stores wherever possible: on
 // this architecture loads and stores share one counter, so a load issued
 // after a store waits for the store to be acknowledged.  The region holds
 // whole 32-row strips (see Staging::NS).  Rows are unpadded, with 16-byte chunks
